@@ -1,0 +1,270 @@
+"""FP64 CPU oracle for the sparse-voxel volume renderer and its gradients.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the product path never does.
+It shares no code with the HIP kernels.  Its C core (``oracle.c``) follows the
+paper's equations one ray at a time in double precision; this module only
+marshals numpy arrays, plus two small textbook pieces in numpy (the SE(3)
+exponential map and an Adam step) used by the tracking pins.
+
+Parity unpinned by the paper: the colour activation, the SH sign/order
+convention, the se(3) pose parametrisation, the default (position-only)
+pose chain, early termination and the TV regulariser are readings; they are
+pinned by finite differences, closed forms and invariants, not by numbers
+the paper prints (it prints none for this path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+NREC = 28
+
+
+def build(verbose=False) -> str:
+    """Compile the oracle with gcc (plain IEEE double, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-o", _LIB_PATH, os.path.join(_HERE, "oracle.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    src = os.path.join(_HERE, "oracle.c")
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        build()
+    lib = C.CDLL(_LIB_PATH)
+    P = C.c_void_p
+    i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+    lib.orc_render.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64, i32,
+                               P, P, P, P]
+    lib.orc_render.restype = None
+    lib.orc_backward.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64, i32,
+                                 i32, P, P, P, P]
+    lib.orc_backward.restype = None
+    lib.orc_loss.argtypes = [i32, P, P, P, P, P, P, i32, f64, P, P, P]
+    lib.orc_loss.restype = None
+    lib.orc_tv.argtypes = [P, P, P, f64, f64, f64, P]
+    lib.orc_tv.restype = f64
+    lib.orc_trace.argtypes = [P, P, f64, P, P, P, P, f64, i32, f64, f64, i32, i32, P, P, P, P, P, P]
+    lib.orc_trace.restype = C.c_int
+    lib.orc_interp.argtypes = [P, P, f64, P, P, P, P, P]
+    lib.orc_interp.restype = None
+    lib.orc_sh_basis.argtypes = [P, P]
+    lib.orc_sh_basis_grad.argtypes = [P, P]
+    lib.orc_ray.argtypes = [P, P, C.c_int, C.c_int, P, P, P]
+    lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _grid_args(grid):
+    R = _c(grid.reso, np.int32)
+    lo = _c(grid.aabb_min, np.float32)
+    link = _c(grid.link, np.int32)
+    data = _c(grid.data, np.float32)
+    return (R, lo, float(grid.voxel_size), link, data)
+
+
+def _ray_args(rays):
+    return (_c(rays.c2w, np.float64), _c(rays.intr, np.float64),
+            _c(rays.frame_offsets, np.int32), _c(rays.pix, np.int32))
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def set_threads(n: int):
+    _load().orc_set_threads(int(n))
+
+
+def render(grid, rays, opts):
+    """Forward render: rgb f64[n,3], z-depth f64[n], nsamp i32[n], stats i64[n,3]."""
+    lib = _load()
+    R, lo, vs, link, data = _grid_args(grid)
+    c2w, intr, off, pix = _ray_args(rays)
+    n = rays.n_rays
+    rgb = np.zeros((n, 3))
+    depth = np.zeros(n)
+    nsamp = np.zeros(n, np.int32)
+    stats = np.zeros((n, 3), np.int64)
+    lib.orc_render(_p(R), _p(lo), vs, _p(link), _p(data), rays.n_frames, _p(c2w), _p(intr),
+                   _p(off), _p(pix), n, opts.step_vox, opts.max_samples, opts.t_near,
+                   opts.t_stop, opts.color_act, _p(rgb), _p(depth), _p(nsamp), _p(stats))
+    return rgb, depth, nsamp, stats
+
+
+def loss(rays, rgb, depth, targets, opts):
+    """Per-frame loss (Eq. 4, 5, 11) and dL/d rgb, dL/d z-depth."""
+    lib = _load()
+    n = rays.n_rays
+    rgb = _c(rgb, np.float64)
+    depth = _c(depth, np.float64)
+    trgb = _c(targets.rgb, np.float32)
+    tdep = _c(targets.depth, np.float32)
+    fw = _c(targets.frame_weight, np.float32)
+    off = _c(rays.frame_offsets, np.int32)
+    L = np.zeros(rays.n_frames)
+    g_rgb = np.zeros((n, 3))
+    g_depth = np.zeros(n)
+    lib.orc_loss(rays.n_frames, _p(off), _p(rgb), _p(depth), _p(trgb), _p(tdep), _p(fw),
+                 opts.depth_loss, float(opts.lambda_depth), _p(L), _p(g_rgb), _p(g_depth))
+    return L, g_rgb, g_depth
+
+
+def backward(grid, rays, opts, g_rgb, g_depth, want_grid=True, want_pose=True, flags=None):
+    """Gradients: grid f64[n_alloc,28] (Eq. 6-10) and pose f64[F,6] (Eq. 12-14)."""
+    lib = _load()
+    R, lo, vs, link, data = _grid_args(grid)
+    c2w, intr, off, pix = _ray_args(rays)
+    g_rgb = _c(g_rgb, np.float64)
+    g_depth = _c(g_depth, np.float64)
+    gd = np.zeros((grid.n_alloc, NREC)) if want_grid else None
+    gp = np.zeros((rays.n_frames, 6)) if want_pose else None
+    fl = opts.flags if flags is None else flags
+    lib.orc_backward(_p(R), _p(lo), vs, _p(link), _p(data), rays.n_frames, _p(c2w), _p(intr),
+                     _p(off), _p(pix), rays.n_rays, opts.step_vox, opts.max_samples, opts.t_near,
+                     opts.t_stop, opts.color_act, int(fl), _p(g_rgb), _p(g_depth), _p(gd), _p(gp))
+    return gd, gp
+
+
+def fused(grid, rays, targets, opts, want_grid=True, want_pose=True):
+    """Forward, loss and backward of one batch, the way a training step runs it."""
+    rgb, depth, nsamp, stats = render(grid, rays, opts)
+    L, g_rgb, g_depth = loss(rays, rgb, depth, targets, opts)
+    gd, gp = backward(grid, rays, opts, g_rgb, g_depth, want_grid, want_pose)
+    return dict(rgb=rgb, depth=depth, nsamp=nsamp, stats=stats, loss=L, g_rgb=g_rgb,
+                g_depth=g_depth, grad_data=gd, grad_pose=gp)
+
+
+def tv(grid, lambda_sigma, lambda_sh, eps, want_grad=True):
+    """Total-variation value and its gradient f64[n_alloc,28]."""
+    lib = _load()
+    R, lo, vs, link, data = _grid_args(grid)
+    g = np.zeros((grid.n_alloc, NREC)) if want_grad else None
+    val = lib.orc_tv(_p(R), _p(link), _p(data), float(lambda_sigma), float(lambda_sh),
+                     float(eps), _p(g))
+    return float(val), g
+
+
+def trace(grid, o, d, opts, cap=4096):
+    """Per-sample record of one ray: t, sigma_raw, colour, T_i (n+1), w, (C-hat, D-hat)."""
+    lib = _load()
+    R, lo, vs, link, data = _grid_args(grid)
+    o = _c(o, np.float64)
+    d = _c(d, np.float64)
+    t = np.zeros(cap)
+    sr = np.zeros(cap)
+    cs = np.zeros((cap, 3))
+    T = np.zeros(cap + 1)
+    w = np.zeros(cap)
+    out = np.zeros(4)
+    n = lib.orc_trace(_p(R), _p(lo), vs, _p(link), _p(data), _p(o), _p(d), opts.step_vox,
+                      opts.max_samples, opts.t_near, opts.t_stop, opts.color_act, cap,
+                      _p(t), _p(sr), _p(cs), _p(T), _p(w), _p(out))
+    n = min(n, cap)
+    return dict(n=n, t=t[:n], sigma_raw=sr[:n], c=cs[:n], T=T[:n + 1], w=w[:n],
+                rgb=out[:3].copy(), D=float(out[3]))
+
+
+def interp(grid, q, want_grad=True):
+    """Interpolated 28 values at voxel point q and their Appendix A gradients."""
+    lib = _load()
+    R, lo, vs, link, data = _grid_args(grid)
+    q = _c(q, np.float64)
+    val = np.zeros(NREC)
+    g = np.zeros((NREC, 3)) if want_grad else None
+    lib.orc_interp(_p(R), _p(lo), vs, _p(link), _p(data), _p(q), _p(val), _p(g))
+    return val, g
+
+
+def sh_basis(d):
+    lib = _load()
+    d = _c(d, np.float64)
+    Y = np.zeros(9)
+    lib.orc_sh_basis(_p(d), _p(Y))
+    return Y
+
+
+def sh_basis_grad(d):
+    lib = _load()
+    d = _c(d, np.float64)
+    G = np.zeros((9, 3))
+    lib.orc_sh_basis_grad(_p(d), _p(G))
+    return G
+
+
+def ray(c2w, intr, u, v):
+    """Camera centre o, unit world direction d and |d_cam| for pixel (u, v)."""
+    lib = _load()
+    c2w = _c(c2w, np.float64)
+    intr = _c(intr, np.float64)
+    o, d, s = np.zeros(3), np.zeros(3), np.zeros(1)
+    lib.orc_ray(_p(c2w), _p(intr), int(u), int(v), _p(o), _p(d), _p(s))
+    return o, d, float(s[0])
+
+
+# ---------------------------------------------------------------------------
+# Tracking update: SE(3) exponential and Adam (textbook forms, numpy FP64)
+# ---------------------------------------------------------------------------
+
+def hat(w):
+    return np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]], np.float64)
+
+
+def se3_exp(xi):
+    """4x4 exp of the twist xi = (rho, phi) (rotation by Rodrigues' formula)."""
+    rho, phi = np.asarray(xi[:3], np.float64), np.asarray(xi[3:], np.float64)
+    th = np.linalg.norm(phi)
+    K = hat(phi)
+    if th < 1e-12:
+        Rm = np.eye(3) + K
+        V = np.eye(3) + 0.5 * K
+    else:
+        Rm = np.eye(3) + np.sin(th) / th * K + (1 - np.cos(th)) / th ** 2 * (K @ K)
+        V = np.eye(3) + (1 - np.cos(th)) / th ** 2 * K + (th - np.sin(th)) / th ** 3 * (K @ K)
+    T = np.eye(4)
+    T[:3, :3] = Rm
+    T[:3, 3] = V @ rho
+    return T
+
+
+def apply_left(xi, c2w):
+    """exp(xi^) * [c2w; 0 0 0 1] as a 3x4 matrix (left, world-frame update)."""
+    T = np.eye(4)
+    T[:3, :] = np.asarray(c2w, np.float64)
+    return (se3_exp(xi) @ T)[:3, :]
+
+
+def adam_pose_step(c2w, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba) on each frame's se(3) tangent, then the
+    left retraction c2w <- exp(-lr * m_hat / (sqrt(v_hat) + eps)) c2w."""
+    m = beta1 * m + (1 - beta1) * grad
+    v = beta2 * v + (1 - beta2) * grad * grad
+    mh = m / (1 - beta1 ** step)
+    vh = v / (1 - beta2 ** step)
+    upd = -lr * mh / (np.sqrt(vh) + eps)
+    out = np.stack([apply_left(upd[f], c2w[f]) for f in range(len(c2w))])
+    return out, m, v
