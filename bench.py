@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the fused forward + backward hot path on one MI355X.
+
+Default workload: one 1200x680 frame (816,000 rays) on the sparse 256^3 room
+grid (~10 % of vertices allocated).  One step is the whole hot path over that
+batch: ray generation, sampling, gathers, compositing, loss, grid gradient
+(mapping) and pose gradient (tracking) in one fused launch, the TV gradient,
+and the Adam pose update.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line (see the design doc for every field).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2307_03404_amd import synth
+    return {"c1": synth.config1, "c2": synth.config2, "c3": synth.config3,
+            "c4": synth.config4, "c5": synth.config5}[name]()
+
+
+def alg_bytes(stats, n_rays, n_frames, want):
+    """Algorithmic bytes of one fused launch (per-ray model, gathers counted
+    without cache reuse): 44 B/ray of ray inputs, targets and outputs, 32 B of
+    links per occupied sample, 112 B per allocated corner gathered, 224 B per
+    gradient corner (read-modify-write of 28 floats) and 24 B per frame."""
+    occ, occ_c, grad_c, valid = (int(x) for x in stats)
+    b = 44 * n_rays + 32 * occ + 112 * occ_c + 24 * n_frames
+    if want & 1:
+        b += 224 * grad_c
+    return b
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The FP64 oracle (forward, loss, grid + pose backward) on a bounded
+    seeded ray sample of the same workload, on this host's cores."""
+    import oracle
+    from paper_2307_03404_amd import synth
+    oracle.build() if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")) else None
+    probe = synth.subset_rays(wl, 4000, seed=21)
+    t0 = time.perf_counter()
+    oracle.fused(probe.grid, probe.rays, probe.targets, probe.opts)
+    dt = time.perf_counter() - t0
+    n = int(min(wl.rays.n_rays, max(4000, 4000 * budget_s / max(dt, 1e-3))))
+    sample = synth.subset_rays(wl, n, seed=22)
+    t0 = time.perf_counter()
+    oracle.fused(sample.grid, sample.rays, sample.targets, sample.opts)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "rays/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} of {wl.rays.n_rays} rays (seeded uniform subset), fwd+loss+grid+pose "
+                      f"backward in FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2307_03404_amd import pxm
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    wl = workload(args.workload)
+    log(f"workload {wl.name}: {wl.rays.n_rays} rays, {wl.rays.n_frames} frames, grid {wl.grid.reso}, "
+        f"{wl.grid.n_alloc} allocated vertices (generated in {time.perf_counter() - t0:.1f} s)")
+    g = pxm.grid_to_device(wl.grid)
+    r = pxm.rays_to_device(wl.rays)
+    trgb = torch.from_numpy(wl.targets.rgb).to(dev)
+    tdep = torch.from_numpy(wl.targets.depth).to(dev)
+    fw = torch.from_numpy(wl.targets.frame_weight).to(dev)
+    n, F = wl.rays.n_rays, wl.rays.n_frames
+    want = pxm.WANT_GRID | pxm.WANT_POSE
+    tv = wl.meta.get("tv", (1e-5, 1e-6, 1e-9))
+    if args.block or args.variant >= 0:
+        pxm.set_tuning(args.block or 256, max(args.variant, 0))
+    block, variant = pxm.get_tuning()
+
+    rgb = torch.empty(n, 3, device=dev)
+    depth = torch.empty(n, device=dev)
+    loss = torch.zeros(F, dtype=torch.float64, device=dev)
+    gd = torch.zeros_like(g.data)
+    gp = torch.zeros(F, 6, dtype=torch.float64, device=dev)
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    adam_state = torch.zeros(F, 16, dtype=torch.float64, device=dev)
+    c2w0 = r.c2w.clone()
+    ws = pxm.new_workspace(g, r, wl.opts, want)
+
+    # one untimed pass with traffic counters for the byte model
+    pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, want | pxm.WANT_STATS, rgb=rgb, depth=depth,
+                     loss=loss, grad_data=gd, grad_pose=gp, stats=stats, ws=ws)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    bytes_launch = alg_bytes(st, n, F, want)
+    log(f"per ray: {st[0] / n:.2f} occupied samples, {st[1] / n:.2f} corner gathers, "
+        f"{st[2] / max(st[3], 1):.2f} gradient corners per valid ray; "
+        f"{bytes_launch / n:.0f} algorithmic bytes/ray")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+
+    def step(i=None):
+        gd.zero_()
+        loss.zero_()
+        if i is not None:
+            ev[i][0].record()
+        pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, want, rgb=rgb, depth=depth, loss=loss,
+                         grad_data=gd, grad_pose=gp, ws=ws)
+        if i is not None:
+            ev[i][1].record()
+        pxm.tv_grad(g, tv[0], tv[1], tv[2], gd)
+        pxm.pose_adam(r.c2w, gp, adam_state, 1e-4)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fused_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    r.c2w.copy_(c2w0)
+
+    # separate timing of the TV and pose-update kernels (reported, not used)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        pxm.tv_grad(g, tv[0], tv[1], tv[2], gd)
+    e1.record()
+    torch.cuda.synchronize()
+    tv_ms = e0.elapsed_time(e1) / 5
+
+    ms = 1e3 * elapsed / args.steps
+    value = n * args.steps / elapsed
+    achieved = bytes_launch / (fused_ms * 1e-3) / 1e9
+    out = {
+        "metric": "fwd+bwd rays/s (mapping & tracking), 1200x680 rays, 256^3 grid; % of HBM peak",
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "rays": n, "frames": F, "grid": list(wl.grid.reso),
+                   "allocated_vertices": wl.grid.n_alloc,
+                   "step": "fused fwd+loss+grid+pose bwd, TV grad, Adam pose update",
+                   "block": block, "variant": variant},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_fused<true,true,false>", "kernel_ms": fused_ms,
+                     "alg_bytes_per_launch": bytes_launch},
+        "kernels_ms": {"fused": fused_ms, "tv": tv_ms},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

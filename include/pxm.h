@@ -1,0 +1,224 @@
+/*
+ * pxm.h -- C ABI of the MI355X (gfx950) kernels for differentiable volume
+ * rendering of a sparse voxel grid, the hot path of "RGB-D Mapping and
+ * Tracking in a Plenoxel Radiance Field" (Teigen et al., WACV 2024).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Every array pointer is DEVICE memory owned by the caller; the
+ *           library never allocates, frees or retains it.  Descriptors
+ *           (pxm_grid, pxm_rays, pxm_opts) are HOST structs read during the
+ *           call only.  Scratch space, where an entry point needs any, comes
+ *           from a caller-provided workspace sized by pxm_workspace_bytes.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *           stream).  Calls only enqueue work and return; results are ready
+ *           when the stream is synchronised.  Nothing inside allocates or
+ *           synchronises, so every call may be captured into a HIP graph.
+ * Outputs.  rgb / depth / nsamp / loss are overwritten.  Every gradient
+ *           output ACCUMULATES (+=): zero it before the first contribution.
+ * Errors.   Each call returns PXM_OK (0) or a positive pxm_status.  All
+ *           argument checks run on the host before anything is enqueued, so
+ *           a rejected call has no effect.  With n_rays == 0 a render call
+ *           is a no-op and its per-ray arrays may be NULL.  pxm_last_error() returns a
+ *           thread-local description of the last failure.  A fault in a
+ *           kernel surfaces at the caller's next stream synchronisation.
+ *           Device-resident metadata (frame_offsets) cannot be checked on the
+ *           host; kernels clamp every index they derive from it so a
+ *           malformed CSR yields wrong numbers, never an out-of-bounds access.
+ *
+ * Grid (Sec. 5.2, model representation).  A lattice of Rx x Ry x Rz
+ * vertices; vertex (i,j,k) sits at aabb_min + voxel_size * (i,j,k).  Each
+ * allocated vertex holds 28 floats: the density followed by nine degree-2
+ * spherical-harmonic coefficients for each colour channel (record[1+9c+k]).
+ * Samples are trilinearly interpolated from the 8 closest vertices (Fig. 4,
+ * Appendix A); an empty vertex (link -1) reads as zero.
+ *
+ * Ray model (Sec. 4).  Pixel (u,v) of frame f defines
+ *   d_cam = ((u + 0.5 - cx) / fx, (v + 0.5 - cy) / fy, 1)  (OpenCV axes),
+ *   d = R d_cam / |d_cam|,  o = t,  with c2w[f] = [R | t] row-major 3x4.
+ * Samples sit at distances t_k = t_near + k * step_vox * voxel_size from o,
+ * k = 0, 1, ...; a sample is kept while its position lies inside the vertex
+ * box [0, R-1]^3 (voxel units), at most max_samples positions counted from
+ * the first kept one.  delta = step_vox is the sample spacing in the
+ * exponent, with density in per-voxel units.
+ */
+#ifndef PXM_H
+#define PXM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PXM_ABI_VERSION 1
+#define PXM_RECORD 28          /* floats per vertex: density + 3 x 9 SH */
+
+typedef enum {
+    PXM_OK = 0,
+    PXM_INVALID_ARGUMENT = 1,    /* null pointer, bad enum, non-finite or out-of-range scalar */
+    PXM_UNSUPPORTED = 2,         /* valid but outside what the kernels handle (e.g. R < 2) */
+    PXM_DEVICE_ERROR = 3,        /* the HIP runtime refused a launch */
+    PXM_WORKSPACE_TOO_SMALL = 4  /* ws_bytes below pxm_workspace_bytes() */
+} pxm_status;
+
+/* Colour activation c = act(s) applied to the SH sum s (the paper leaves it open). */
+enum { PXM_COLOR_RELU_SHIFT = 0,   /* max(s + 0.5, 0) */
+       PXM_COLOR_SIGMOID = 1,      /* 1 / (1 + exp(-s)) */
+       PXM_COLOR_IDENTITY = 2 };   /* s */
+
+/* Penalty rho on the z-depth residual: Eq. 5 is squared; L1 is the metric of Sec. 6.1. */
+enum { PXM_DEPTH_L1 = 0, PXM_DEPTH_L2 = 1 };
+
+/* pxm_opts.flags */
+enum { PXM_FLAG_POSE_VIEWDIR = 1 };  /* add the exact d(colour)/d(view direction) term to the
+                                        rotation gradient; Eq. 12 omits it (default off) */
+
+/* pxm_render_fused `want` bits */
+enum { PXM_WANT_GRID = 1,    /* accumulate grad_data */
+       PXM_WANT_POSE = 2,    /* accumulate grad_pose */
+       PXM_WANT_STATS = 4 }; /* accumulate the traffic counters into `stats` */
+
+typedef struct {
+    int32_t reso[3];        /* vertices per axis, each >= 2 */
+    float aabb_min[3];      /* world position of vertex (0,0,0) */
+    float voxel_size;       /* world edge length of one voxel, > 0 */
+    const int32_t *link;    /* [Rx*Ry*Rz], index (x*Ry + y)*Rz + z -> record id or -1 */
+    int64_t n_alloc;        /* number of records */
+    const float *data;      /* [n_alloc][28], 16-byte aligned */
+} pxm_grid;
+
+typedef struct {
+    int32_t n_frames;              /* F >= 1 */
+    const float *c2w;              /* [F][3][4] camera-to-world, row-major */
+    const float *intr;             /* [F][4] fx, fy, cx, cy (pixels) */
+    int64_t n_rays;                /* total rays, >= 0 */
+    const int32_t *frame_offsets;  /* [F+1] CSR: rays of frame f are [off[f], off[f+1]),
+                                      off[0] = 0, non-decreasing, off[F] = n_rays */
+    const int32_t *pix;            /* [n_rays][2] pixel (u, v) */
+} pxm_rays;
+
+typedef struct {
+    float step_vox;         /* sample spacing in voxels, > 0 (0.5 in every workload here) */
+    int32_t max_samples;    /* cap on kept sample positions per ray, >= 1 */
+    float t_near;           /* distance of sample k = 0 from the camera centre, >= 0 */
+    float t_stop;           /* stop after sample i once T_{i+1} < t_stop; 0 <= t_stop < 1 */
+    int32_t color_act;      /* PXM_COLOR_* */
+    int32_t depth_loss;     /* PXM_DEPTH_* (used by pxm_render_fused) */
+    float lambda_depth;     /* lambda_d of Eq. 11 (used by pxm_render_fused) */
+    int32_t flags;          /* PXM_FLAG_* */
+} pxm_opts;
+
+/*
+ * Forward render, Eq. 1-3 (Sec. 4).  For every ray: the composited colour
+ * C-hat = sum_i T_i (1 - exp(-sigma_i delta)) c_i, the expected depth
+ * D-hat = sum_i T_i (1 - exp(-sigma_i delta)) t_i reported as z-depth
+ * D-hat / |d_cam|, and the number of sample positions kept (nsamp), which
+ * the backward passes replay.  sigma_i = max(interpolated density, 0),
+ * c_i = act(sum_k Y_k(d) * interpolated SH_k) per channel.
+ *   rgb   [n_rays][3] f32 out,   depth [n_rays] f32 out,   nsamp [n_rays] i32 out
+ */
+int pxm_render_forward(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
+                       float *rgb, float *depth, int32_t *nsamp, void *stream);
+
+/*
+ * Mapping backward, Eq. 6-10 (Sec. 5.2).  Given the forward outputs and the
+ * upstream gradients g_rgb = dL/dC-hat [n_rays][3] and g_depth = dL/d(z-depth)
+ * [n_rays], recomputes each ray's samples and adds
+ *   dL/d sigma_raw,i = 1[sigma_raw,i > 0] delta [g_C.(c_i T_{i+1} - C-hat + sum_{j<=i} c_j w_j)
+ *                                                + g_D (t_i T_{i+1} - D-hat + sum_{j<=i} t_j w_j)]
+ *   dL/d SH_k,c,i    = act'(s_c,i) w_i g_C,c Y_k(d)
+ * through the trilinear weights into grad_data [n_alloc][28] (accumulated;
+ * empty vertices receive nothing).  Rays with all-zero upstream gradients are skipped.
+ */
+int pxm_render_backward_grid(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
+                             const float *rgb, const float *depth, const int32_t *nsamp,
+                             const float *g_rgb, const float *g_depth, float *grad_data,
+                             void *stream);
+
+/*
+ * Tracking backward, Eq. 12-14 (Sec. 5.3) with the Appendix A spatial
+ * gradients of the trilinear interpolant.  For each ray,
+ *   g_p,i = dL/d sigma_raw,i * grad sigma_raw(p_i) + sum_c dL/ds_c,i * grad s_c(p_i),
+ *   g_o = sum_i g_p,i,  g_d = sum_i t_i g_p,i   (dp/do = 1, dp/dd = t_i),
+ * and the gradient with respect to a left, world-frame perturbation
+ * exp(xi^) c2w, xi = (rho, phi), is (g_o, o x g_o + d x g_d); these are summed
+ * over each frame's rays into grad_pose [F][6] (float64, accumulated).  With
+ * PXM_FLAG_POSE_VIEWDIR the exact term d x (dL/dd through the SH basis) is
+ * added to phi.
+ */
+int pxm_render_backward_pose(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
+                             const float *rgb, const float *depth, const int32_t *nsamp,
+                             const float *g_rgb, const float *g_depth, double *grad_pose,
+                             void *stream);
+
+/*
+ * Total-variation gradient over the allocated vertices (the Plenoxel-style
+ * regulariser; the paper does not define one):
+ *   TV = sum_m lambda_m sum_v sqrt(dx_m(v)^2 + dy_m(v)^2 + dz_m(v)^2 + eps),
+ * forward differences to the +x/+y/+z neighbours (empty reads as 0), v
+ * allocated and not on an upper face, lambda_0 = lambda_density for the
+ * density field and lambda_sh for each of the 27 SH fields.  dTV/d record is
+ * added into grad_data [n_alloc][28] (accumulated, gather form: one writer
+ * per vertex, no atomics).
+ */
+int pxm_tv_grad(const pxm_grid *grid, float lambda_density, float lambda_sh, float eps,
+                float *grad_data, void *stream);
+
+/*
+ * Fused batched step: forward (Eq. 1-3), the loss of Eq. 4, 5 and 11, and the
+ * mapping and/or tracking backward for every ray of every frame in ONE
+ * launch.  A ray whose target depth is non-finite or <= 0 is dropped from
+ * the loss (Sec. 6.1).  Per frame f, with w_f = frame_weight[f] (1/M):
+ *   L_f = w_f sum_r |C-hat_r - C_r|^2 + lambda_depth w_f sum_r rho(z_r - D_r).
+ *   tgt_rgb [n_rays][3], tgt_depth [n_rays], frame_weight [F]      (in)
+ *   rgb, depth   [n_rays][3], [n_rays]       (out, may be NULL)
+ *   loss         [F] float64                 (accumulated, may be NULL)
+ *   grad_data    [n_alloc][28]               (accumulated; required with PXM_WANT_GRID)
+ *   grad_pose    [F][6] float64              (accumulated; required with PXM_WANT_POSE)
+ *   stats        [4] int64                   (accumulated with PXM_WANT_STATS:
+ *                 occupied samples, allocated corners of those, allocated
+ *                 corners that received a gradient, rays with a valid target)
+ * ws / ws_bytes: workspace of at least pxm_workspace_bytes(..., want) bytes.
+ */
+int pxm_render_fused(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
+                     const float *tgt_rgb, const float *tgt_depth, const float *frame_weight,
+                     int32_t want, float *rgb, float *depth, double *loss, float *grad_data,
+                     double *grad_pose, int64_t *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Tracking update (Sec. 5.4: Adam for tracking): per frame, one Adam step
+ * (beta1, beta2, eps; bias-corrected with the frame's own step counter) on
+ * the se(3) tangent xi = -lr m_hat / (sqrt(v_hat) + eps), then the left
+ * retraction c2w <- exp(xi^) c2w.  grad_pose is read and then zeroed, so a
+ * captured graph needs no separate clearing node.
+ *   c2w [F][3][4] f32 (in/out), grad_pose [F][6] f64 (in, zeroed),
+ *   state [F][16] f64 (in/out: m[6], v[6], step count, 3 unused; start zeroed)
+ */
+int pxm_pose_adam(int32_t n_frames, float *c2w, double *grad_pose, double *state, float lr,
+                  float beta1, float beta2, float eps, void *stream);
+
+/* Workspace bytes pxm_render_fused needs for these arguments and `want`. */
+size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
+                           int32_t want);
+
+/*
+ * Launch tuning for pxm_render_fused (process-wide; read at each call):
+ *   block    rays per workgroup (64, 128, 256 or 512; 0 = default 256)
+ *   variant  0 = one workgroup per ray tile, 1 = persistent workgroups
+ *            pulling ray tiles from a device counter in the workspace
+ * Returns PXM_INVALID_ARGUMENT for values outside these sets.
+ */
+int pxm_set_tuning(int32_t block, int32_t variant);
+void pxm_get_tuning(int32_t *block, int32_t *variant);
+
+const char *pxm_status_string(int status);
+const char *pxm_last_error(void);
+int pxm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PXM_H */

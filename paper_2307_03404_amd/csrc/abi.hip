@@ -1,0 +1,256 @@
+// C ABI of libpxm: host-side argument checks, then one launch per call.
+// Nothing here allocates device memory or synchronises a stream.
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "../../include/pxm.h"
+#include "internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+std::atomic<int> g_block{256};
+std::atomic<int> g_variant{0};
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+bool finite(float v) { return std::isfinite(v); }
+
+int check_grid(const pxm_grid* g, bool need_payload = true) {
+    if (!g) return fail(PXM_INVALID_ARGUMENT, "grid is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (g->reso[a] < 2) return fail(PXM_UNSUPPORTED, "grid reso[%d] = %d < 2", a, g->reso[a]);
+        if (!finite(g->aabb_min[a])) return fail(PXM_INVALID_ARGUMENT, "aabb_min[%d] not finite", a);
+    }
+    const long double cells = (long double)g->reso[0] * g->reso[1] * g->reso[2];
+    if (cells > 9.0e18L) return fail(PXM_UNSUPPORTED, "lattice too large");
+    if (!(g->voxel_size > 0.f) || !finite(g->voxel_size))
+        return fail(PXM_INVALID_ARGUMENT, "voxel_size must be finite and > 0");
+    if (!g->link) return fail(PXM_INVALID_ARGUMENT, "grid.link is NULL");
+    if (g->n_alloc < 0 || g->n_alloc > 2147483647LL)
+        return fail(PXM_INVALID_ARGUMENT, "n_alloc = %lld outside [0, 2^31)", (long long)g->n_alloc);
+    if (need_payload && !g->data) return fail(PXM_INVALID_ARGUMENT, "grid.data is NULL");
+    if (g->data && (reinterpret_cast<uintptr_t>(g->data) & 15))
+        return fail(PXM_INVALID_ARGUMENT, "grid.data must be 16-byte aligned");
+    return PXM_OK;
+}
+
+int check_rays(const pxm_rays* r) {
+    if (!r) return fail(PXM_INVALID_ARGUMENT, "rays is NULL");
+    if (r->n_frames < 1) return fail(PXM_INVALID_ARGUMENT, "n_frames = %d < 1", r->n_frames);
+    if (r->n_rays < 0) return fail(PXM_INVALID_ARGUMENT, "n_rays < 0");
+    if (r->n_rays > 2147483647LL) return fail(PXM_UNSUPPORTED, "n_rays beyond int32 offsets");
+    if (!r->c2w || !r->intr || !r->frame_offsets)
+        return fail(PXM_INVALID_ARGUMENT, "rays.c2w / intr / frame_offsets is NULL");
+    if (r->n_rays > 0 && !r->pix) return fail(PXM_INVALID_ARGUMENT, "rays.pix is NULL");
+    return PXM_OK;
+}
+
+int check_opts(const pxm_opts* o) {
+    if (!o) return fail(PXM_INVALID_ARGUMENT, "opts is NULL");
+    if (!(o->step_vox > 0.f) || !finite(o->step_vox))
+        return fail(PXM_INVALID_ARGUMENT, "step_vox must be finite and > 0");
+    if (o->max_samples < 1) return fail(PXM_INVALID_ARGUMENT, "max_samples < 1");
+    if (!(o->t_near >= 0.f) || !finite(o->t_near)) return fail(PXM_INVALID_ARGUMENT, "t_near must be finite and >= 0");
+    if (!(o->t_stop >= 0.f && o->t_stop < 1.f)) return fail(PXM_INVALID_ARGUMENT, "t_stop outside [0, 1)");
+    if (o->color_act < 0 || o->color_act > 2) return fail(PXM_INVALID_ARGUMENT, "color_act = %d", o->color_act);
+    if (o->depth_loss < 0 || o->depth_loss > 1) return fail(PXM_INVALID_ARGUMENT, "depth_loss = %d", o->depth_loss);
+    if (!finite(o->lambda_depth)) return fail(PXM_INVALID_ARGUMENT, "lambda_depth not finite");
+    if (o->flags & ~PXM_FLAG_POSE_VIEWDIR) return fail(PXM_INVALID_ARGUMENT, "unknown flags 0x%x", o->flags);
+    return PXM_OK;
+}
+
+pxm::KGrid kgrid(const pxm_grid* g) {
+    pxm::KGrid k;
+    for (int a = 0; a < 3; ++a) {
+        k.R[a] = g->reso[a];
+        k.lo[a] = (double)g->aabb_min[a];
+    }
+    k.sy = g->reso[2];
+    k.sx = (int64_t)g->reso[1] * g->reso[2];
+    k.vs = g->voxel_size;
+    k.inv_vs = 1.0 / (double)g->voxel_size;
+    k.n_alloc = g->n_alloc;
+    k.link = g->link;
+    k.data = g->data;
+    return k;
+}
+
+pxm::KRays krays(const pxm_rays* r) {
+    pxm::KRays k;
+    k.F = r->n_frames;
+    k.n = r->n_rays;
+    k.c2w = r->c2w;
+    k.intr = r->intr;
+    k.off = r->frame_offsets;
+    k.pix = r->pix;
+    return k;
+}
+
+pxm::KOpts kopts(const pxm_opts* o) {
+    pxm::KOpts k;
+    k.step_vox = o->step_vox;
+    k.max_samples = o->max_samples;
+    k.t_near = o->t_near;
+    k.t_stop = o->t_stop;
+    k.act = o->color_act;
+    k.depth_loss = o->depth_loss;
+    k.lambda_d = o->lambda_depth;
+    k.flags = o->flags;
+    return k;
+}
+
+int launched(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(PXM_DEVICE_ERROR, "%s: %s", what, hipGetErrorString(e));
+    g_err[0] = 0;
+    return PXM_OK;
+}
+
+#define PXM_TRY(x)                 \
+    do {                           \
+        int _s = (x);              \
+        if (_s != PXM_OK) return _s; \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int pxm_abi_version(void) { return PXM_ABI_VERSION; }
+
+const char* pxm_last_error(void) { return g_err; }
+
+const char* pxm_status_string(int s) {
+    switch (s) {
+        case PXM_OK: return "ok";
+        case PXM_INVALID_ARGUMENT: return "invalid argument";
+        case PXM_UNSUPPORTED: return "unsupported";
+        case PXM_DEVICE_ERROR: return "device error";
+        case PXM_WORKSPACE_TOO_SMALL: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+int pxm_set_tuning(int32_t block, int32_t variant) {
+    if (block == 0) block = 256;
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(PXM_INVALID_ARGUMENT, "block = %d not in {64,128,256,512}", block);
+    if (variant != 0 && variant != 1) return fail(PXM_INVALID_ARGUMENT, "variant = %d not in {0,1}", variant);
+    g_block.store(block);
+    g_variant.store(variant);
+    return PXM_OK;
+}
+
+void pxm_get_tuning(int32_t* block, int32_t* variant) {
+    if (block) *block = g_block.load();
+    if (variant) *variant = g_variant.load();
+}
+
+int pxm_render_forward(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
+                       float* rgb, float* depth, int32_t* nsamp, void* stream) {
+    PXM_TRY(check_grid(grid));
+    PXM_TRY(check_rays(rays));
+    PXM_TRY(check_opts(opts));
+    if (rays->n_rays == 0) return PXM_OK;
+    if (!rgb || !depth || !nsamp) return fail(PXM_INVALID_ARGUMENT, "rgb / depth / nsamp is NULL");
+    return launched(pxm::launch_forward(kgrid(grid), krays(rays), kopts(opts), rgb, depth, nsamp,
+                                        (hipStream_t)stream), "render_forward");
+}
+
+int pxm_render_backward_grid(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
+                             const float* rgb, const float* depth, const int32_t* nsamp,
+                             const float* g_rgb, const float* g_depth, float* grad_data,
+                             void* stream) {
+    PXM_TRY(check_grid(grid));
+    PXM_TRY(check_rays(rays));
+    PXM_TRY(check_opts(opts));
+    if (!grad_data) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
+    if (rays->n_rays == 0) return PXM_OK;
+    if (!rgb || !depth || !nsamp || !g_rgb || !g_depth)
+        return fail(PXM_INVALID_ARGUMENT, "a required array is NULL");
+    return launched(pxm::launch_backward(kgrid(grid), krays(rays), kopts(opts), rgb, depth, nsamp,
+                                         g_rgb, g_depth, grad_data, nullptr, (hipStream_t)stream),
+                    "render_backward_grid");
+}
+
+int pxm_render_backward_pose(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
+                             const float* rgb, const float* depth, const int32_t* nsamp,
+                             const float* g_rgb, const float* g_depth, double* grad_pose,
+                             void* stream) {
+    PXM_TRY(check_grid(grid));
+    PXM_TRY(check_rays(rays));
+    PXM_TRY(check_opts(opts));
+    if (!grad_pose) return fail(PXM_INVALID_ARGUMENT, "grad_pose is NULL");
+    if (rays->n_rays == 0) return PXM_OK;
+    if (!rgb || !depth || !nsamp || !g_rgb || !g_depth)
+        return fail(PXM_INVALID_ARGUMENT, "a required array is NULL");
+    return launched(pxm::launch_backward(kgrid(grid), krays(rays), kopts(opts), rgb, depth, nsamp,
+                                         g_rgb, g_depth, nullptr, grad_pose, (hipStream_t)stream),
+                    "render_backward_pose");
+}
+
+int pxm_tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, float eps,
+                float* grad_data, void* stream) {
+    PXM_TRY(check_grid(grid));
+    if (!grad_data) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
+    if (!finite(lambda_density) || !finite(lambda_sh))
+        return fail(PXM_INVALID_ARGUMENT, "lambda not finite");
+    if (!(eps > 0.f) || !finite(eps)) return fail(PXM_INVALID_ARGUMENT, "eps must be finite and > 0");
+    if (reinterpret_cast<uintptr_t>(grad_data) & 15)
+        return fail(PXM_INVALID_ARGUMENT, "grad_data must be 16-byte aligned");
+    return launched(pxm::launch_tv(kgrid(grid), lambda_density, lambda_sh, eps, grad_data,
+                                   (hipStream_t)stream), "tv_grad");
+}
+
+size_t pxm_workspace_bytes(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
+                           int32_t want) {
+    (void)grid; (void)rays; (void)opts; (void)want;
+    return pxm::FUSED_WS_BYTES;
+}
+
+int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
+                     const float* tgt_rgb, const float* tgt_depth, const float* frame_weight,
+                     int32_t want, float* rgb, float* depth, double* loss, float* grad_data,
+                     double* grad_pose, int64_t* stats, void* ws, size_t ws_bytes, void* stream) {
+    PXM_TRY(check_grid(grid));
+    PXM_TRY(check_rays(rays));
+    PXM_TRY(check_opts(opts));
+    if (want & ~(PXM_WANT_GRID | PXM_WANT_POSE | PXM_WANT_STATS))
+        return fail(PXM_INVALID_ARGUMENT, "unknown want bits 0x%x", want);
+    if (rays->n_rays > 0 && (!tgt_rgb || !tgt_depth || !frame_weight))
+        return fail(PXM_INVALID_ARGUMENT, "targets / frame_weight is NULL");
+    if ((want & PXM_WANT_GRID) && !grad_data) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
+    if ((want & PXM_WANT_POSE) && !grad_pose) return fail(PXM_INVALID_ARGUMENT, "grad_pose is NULL");
+    if ((want & PXM_WANT_STATS) && !stats) return fail(PXM_INVALID_ARGUMENT, "stats is NULL");
+    const size_t need = pxm_workspace_bytes(grid, rays, opts, want);
+    if (!ws) return fail(PXM_INVALID_ARGUMENT, "workspace is NULL");
+    if (ws_bytes < need) return fail(PXM_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (rays->n_rays == 0) return PXM_OK;
+    const int block = g_block.load(), variant = g_variant.load();
+    return launched(pxm::launch_fused(kgrid(grid), krays(rays), kopts(opts), tgt_rgb, tgt_depth,
+                                      frame_weight, want, rgb, depth, loss, grad_data, grad_pose,
+                                      stats, reinterpret_cast<unsigned*>(ws), block, variant,
+                                      (hipStream_t)stream), "render_fused");
+}
+
+int pxm_pose_adam(int32_t n_frames, float* c2w, double* grad_pose, double* state, float lr,
+                  float beta1, float beta2, float eps, void* stream) {
+    if (n_frames < 1) return fail(PXM_INVALID_ARGUMENT, "n_frames < 1");
+    if (!c2w || !grad_pose || !state) return fail(PXM_INVALID_ARGUMENT, "a required array is NULL");
+    if (!(lr >= 0.f) || !finite(lr)) return fail(PXM_INVALID_ARGUMENT, "lr must be finite and >= 0");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+        return fail(PXM_INVALID_ARGUMENT, "betas outside [0, 1)");
+    if (!(eps > 0.f) || !finite(eps)) return fail(PXM_INVALID_ARGUMENT, "eps must be finite and > 0");
+    return launched(pxm::launch_adam(n_frames, c2w, grad_pose, state, lr, beta1, beta2, eps,
+                                     (hipStream_t)stream), "pose_adam");
+}
+
+}  // extern "C"

@@ -1,0 +1,34 @@
+// Host-side launchers shared by the C ABI translation unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kcommon.hpp"
+
+namespace pxm {
+
+// Fused-kernel workspace: tile counter and finished-workgroup counter of the
+// persistent variant.  The kernel leaves both at zero when it completes.
+constexpr size_t FUSED_WS_BYTES = 256;
+
+hipError_t launch_forward(const KGrid& g, const KRays& rs, const KOpts& op, float* rgb,
+                          float* depth, int32_t* nsamp, hipStream_t st);
+
+hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, const float* rgb,
+                           const float* depth, const int32_t* nsamp, const float* g_rgb,
+                           const float* g_depth, float* grad_data, double* grad_pose,
+                           hipStream_t st);
+
+hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,
+                        const float* tgt_depth, const float* frame_weight, int want, float* rgb,
+                        float* depth, double* loss, float* grad_data, double* grad_pose,
+                        int64_t* stats, unsigned* ws, int block, int variant, hipStream_t st);
+
+hipError_t launch_tv(const KGrid& g, float lambda_density, float lambda_sh, float eps,
+                     float* grad_data, hipStream_t st);
+
+hipError_t launch_adam(int F, float* c2w, double* grad_pose, double* state, float lr, float b1,
+                       float b2, float eps, hipStream_t st);
+
+}  // namespace pxm

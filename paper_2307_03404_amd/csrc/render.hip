@@ -1,0 +1,474 @@
+// Forward, backward and fused kernels of the sparse-voxel volume renderer.
+//
+// One lane per ray.  A wave holds 64 rays of one pixel tile (the ray packer
+// orders full frames in 8x8 tiles), so the lanes gather nearly the same
+// vertices at the same sample index and share cache lines.
+//
+// Forward (Eq. 1-3): march the kept sample positions, skip cells whose 8
+// corners are all empty (exact: they interpolate to zero density) and
+// composite colour and range.  Backward (Eq. 6-14): replay exactly the
+// forward's nsamp positions, re-deriving sigma, c, w and T_{i+1} (nothing is
+// stored per sample), and scatter or reduce the gradients.
+#include "internal.hpp"
+
+namespace pxm {
+
+struct FwdResult {
+    float C[3];
+    float D;            // expected range (world units), Eq. 3
+    int n;              // kept sample positions
+    long long occ;      // samples in cells with an allocated corner
+    long long occ_corners;
+    long long grad_corners;   // allocated corners of samples with sigma_raw > 0
+};
+
+// Forward march of one ray.
+__device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, const Ray& ray,
+                                            const float Y[9], FwdResult& out) {
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, T = 1.f;
+    double L = 0.0;
+    int n = 0;
+    long long occ = 0, occc = 0, gradc = 0;
+    if (!ray.empty) {
+        const float delta = op.step_vox;
+        for (int64_t k = ray.k_first; n < op.max_samples; ++k) {
+            Sample s;
+            if (!sample_at(g, ray, k, s)) break;
+            ++n;
+            int idx[8];
+            const int na = load_links(g, s.base, idx);
+            if (na == 0) continue;
+            CornerVals cv;
+            load_corner_vals(g, idx, Y, cv);
+            float w[8];
+            trilinear_weights(s.f, w);
+            float sr = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                sr = fmaf(w[b], cv.sig[b], sr);
+                s0 = fmaf(w[b], cv.e[b][0], s0);
+                s1 = fmaf(w[b], cv.e[b][1], s1);
+                s2 = fmaf(w[b], cv.e[b][2], s2);
+            }
+            ++occ;
+            occc += na;
+            if (!(sr > 0.f)) continue;
+            gradc += na;
+            const float x = sr * delta;
+            const float wt = T * (-expm1f(-x));
+            C0 = fmaf(wt, act_fwd(op.act, s0), C0);
+            C1 = fmaf(wt, act_fwd(op.act, s1), C1);
+            C2 = fmaf(wt, act_fwd(op.act, s2), C2);
+            D = fmaf(wt, s.t, D);
+            L += (double)x;
+            T = trans_of(L);
+            if (T < op.t_stop) break;
+        }
+    }
+    out.C[0] = C0; out.C[1] = C1; out.C[2] = C2;
+    out.D = D;
+    out.n = n;
+    out.occ = occ;
+    out.occ_corners = occc;
+    out.grad_corners = gradc;
+}
+
+struct PoseAcc {
+    float go[3];        // dL/do summed over samples (Eq. 14: dp/do = 1)
+    float gd[3];        // dL/dd through positions (dp/dd = t_i)
+    float gv[3];        // dL/dd through the SH basis (optional exact term)
+};
+
+// Backward march of one ray over its first n kept positions (Eq. 6-14).
+//   Chat, Dhat: the forward's colour and expected range
+//   gC, gDr:    dL/dC-hat and dL/d(range)
+template <bool GRID, bool POSE, bool VIEW>
+__device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, const Ray& ray,
+                                             const float Y[9], int n, const float Chat[3],
+                                             float Dhat, const float gC[3], float gDr,
+                                             float* __restrict__ grad, PoseAcc& pa) {
+    float GY[9][3];
+    if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
+    float A0 = 0.f, A1 = 0.f, A2 = 0.f, AD = 0.f, T = 1.f;
+    double L = 0.0;
+    const float delta = op.step_vox;
+    const float inv_vs = (float)g.inv_vs;
+    int64_t k = ray.k_first;
+    for (int i = 0; i < n; ++i, ++k) {
+        Sample s;
+        if (!sample_at(g, ray, k, s)) break;
+        int idx[8];
+        if (load_links(g, s.base, idx) == 0) continue;
+        CornerVals cv;
+        float ev[8][3][3];      // per corner, channel: sum_k dY_k/dd * SH_k (VIEW only)
+        if (VIEW) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                cv.sig[b] = 0.f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    cv.e[b][c] = 0.f;
+                    ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
+                }
+                if (idx[b] >= 0) {
+                    float rec[REC];
+                    load_record(g.data, idx[b], rec);
+                    cv.sig[b] = rec[0];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+                        for (int kk = 0; kk < 9; ++kk) {
+                            const float sh = rec[1 + 9 * c + kk];
+                            acc = fmaf(Y[kk], sh, acc);
+                            a0 = fmaf(GY[kk][0], sh, a0);
+                            a1 = fmaf(GY[kk][1], sh, a1);
+                            a2 = fmaf(GY[kk][2], sh, a2);
+                        }
+                        cv.e[b][c] = acc;
+                        ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
+                    }
+                }
+            }
+        } else {
+            load_corner_vals(g, idx, Y, cv);
+        }
+        float w[8];
+        trilinear_weights(s.f, w);
+        float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            sr = fmaf(w[b], cv.sig[b], sr);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
+        }
+        if (!(sr > 0.f)) continue;      // sigma = 0: no light, zero gradient (ReLU)
+        const float x = sr * delta;
+        const float wt = T * (-expm1f(-x));
+        L += (double)x;
+        const float Tn = trans_of(L);
+        float c[3], gs[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            c[ch] = act_fwd(op.act, sc[ch]);
+            gs[ch] = act_bwd(op.act, sc[ch]) * wt * gC[ch];      // Eq. 8 through act
+        }
+        A0 = fmaf(wt, c[0], A0);
+        A1 = fmaf(wt, c[1], A1);
+        A2 = fmaf(wt, c[2], A2);
+        AD = fmaf(wt, s.t, AD);
+        // Eq. 9 and Eq. 10 with inclusive prefixes A = sum_{j<=i} c_j w_j
+        const float gsig = delta * (gC[0] * (c[0] * Tn - Chat[0] + A0)
+                                  + gC[1] * (c[1] * Tn - Chat[1] + A1)
+                                  + gC[2] * (c[2] * Tn - Chat[2] + A2)
+                                  + gDr * (s.t * Tn - Dhat + AD));
+        if (GRID) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (idx[b] < 0) continue;
+                float* __restrict__ p = grad + (int64_t)idx[b] * REC;
+                unsafeAtomicAdd(p, w[b] * gsig);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float gb = w[b] * gs[ch];
+#pragma unroll
+                    for (int kk = 0; kk < 9; ++kk) unsafeAtomicAdd(p + 1 + 9 * ch + kk, gb * Y[kk]);
+                }
+            }
+        }
+        if (POSE) {
+            // Appendix A: grad of the interpolant = sum_b grad(w_b) v_b; fold the
+            // sample's upstream gradients into one value per corner first.
+            float h[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                h[b] = gsig * cv.sig[b] + gs[0] * cv.e[b][0] + gs[1] * cv.e[b][1] + gs[2] * cv.e[b][2];
+            const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
+            const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
+            // d/dfx: (h[1jk] - h[0jk]) weighted by wy_j wz_k, etc.
+            const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
+                           + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
+            const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
+                           + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
+            const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
+                           + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
+            const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                pa.go[a] += gp[a];
+                pa.gd[a] = fmaf(s.t, gp[a], pa.gd[a]);
+            }
+            if (VIEW) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+                        acc = fmaf(w[b], gs[0] * ev[b][0][a] + gs[1] * ev[b][1][a] + gs[2] * ev[b][2][a], acc);
+                    pa.gv[a] += acc;
+                }
+            }
+        }
+        T = Tn;
+    }
+}
+
+// (g_rho, g_phi) of one ray: rho = g_o, phi = o x g_o + d x g_d (+ d x g_view).
+template <bool VIEW>
+__device__ __forceinline__ void pose_six(const Ray& ray, const PoseAcc& pa, double out[6]) {
+    const float* o = ray.o;
+    const float* d = ray.d;
+    float gd[3] = {pa.gd[0], pa.gd[1], pa.gd[2]};
+    if (VIEW) { gd[0] += pa.gv[0]; gd[1] += pa.gv[1]; gd[2] += pa.gv[2]; }
+    out[0] = pa.go[0];
+    out[1] = pa.go[1];
+    out[2] = pa.go[2];
+    out[3] = (double)(o[1] * pa.go[2] - o[2] * pa.go[1]) + (double)(d[1] * gd[2] - d[2] * gd[1]);
+    out[4] = (double)(o[2] * pa.go[0] - o[0] * pa.go[2]) + (double)(d[2] * gd[0] - d[0] * gd[2]);
+    out[5] = (double)(o[0] * pa.go[1] - o[1] * pa.go[0]) + (double)(d[0] * gd[1] - d[1] * gd[0]);
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_forward(KGrid g, KRays rs, KOpts op, float* __restrict__ rgb,
+                                                 float* __restrict__ depth, int32_t* __restrict__ nsamp) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rs.n) return;
+    const int f = frame_of(rs.off, rs.F, r);
+    Ray ray;
+    setup_ray(g, rs, op, r, f, ray);
+    float Y[9];
+    sh9(ray.d[0], ray.d[1], ray.d[2], Y);
+    FwdResult fr;
+    ray_forward(g, op, ray, Y, fr);
+    rgb[3 * r] = fr.C[0];
+    rgb[3 * r + 1] = fr.C[1];
+    rgb[3 * r + 2] = fr.C[2];
+    depth[r] = fr.D / ray.s;
+    nsamp[r] = fr.n;
+}
+
+template <bool GRID, bool POSE, bool VIEW>
+__global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
+                                                  const float* __restrict__ rgb,
+                                                  const float* __restrict__ depth,
+                                                  const int32_t* __restrict__ nsamp,
+                                                  const float* __restrict__ g_rgb,
+                                                  const float* __restrict__ g_depth,
+                                                  float* __restrict__ grad,
+                                                  double* __restrict__ grad_pose) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool active = r < rs.n;
+    int f = 0;
+    Ray ray;
+    PoseAcc pa = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    if (active) {
+        const float gC[3] = {g_rgb[3 * r], g_rgb[3 * r + 1], g_rgb[3 * r + 2]};
+        const float gD = g_depth[r];
+        active = gC[0] != 0.f || gC[1] != 0.f || gC[2] != 0.f || gD != 0.f;
+        if (active) {
+            f = frame_of(rs.off, rs.F, r);
+            setup_ray(g, rs, op, r, f, ray);
+            float Y[9];
+            sh9(ray.d[0], ray.d[1], ray.d[2], Y);
+            const float Chat[3] = {rgb[3 * r], rgb[3 * r + 1], rgb[3 * r + 2]};
+            const float Dhat = depth[r] * ray.s;
+            ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, nsamp[r], Chat, Dhat, gC, gD / ray.s,
+                                           grad, pa);
+        }
+    }
+    if (POSE) {
+        double six[6] = {0, 0, 0, 0, 0, 0};
+        if (active) pose_six<VIEW>(ray, pa, six);
+        seg_sum_atomic<6>(f, active, six, grad_pose);
+    }
+}
+
+// Workgroup -> ray tile, grouping consecutive tiles on one XCD: the hardware
+// deals workgroups round-robin over the 8 XCDs, each with its own L2, and
+// neighbouring tiles gather the same vertices.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+    const int64_t q = G / 8, rem = G % 8;
+    const int64_t x = b % 8, j = b / 8;
+    const int64_t start = x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;
+    return start + j;
+}
+
+template <bool GRID, bool POSE, bool VIEW>
+__global__ void __launch_bounds__(512) k_fused(KGrid g, KRays rs, KOpts op,
+                                               const float* __restrict__ tgt_rgb,
+                                               const float* __restrict__ tgt_depth,
+                                               const float* __restrict__ fw,
+                                               float* __restrict__ rgb_out,
+                                               float* __restrict__ depth_out,
+                                               double* __restrict__ loss,
+                                               float* __restrict__ grad,
+                                               double* __restrict__ grad_pose,
+                                               int64_t* __restrict__ stats,
+                                               unsigned* __restrict__ ws, int persistent) {
+    __shared__ int64_t s_tile;
+    const int64_t n_tiles = (rs.n + blockDim.x - 1) / blockDim.x;
+    for (;;) {
+        int64_t tile;
+        if (persistent) {
+            if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(ws, 1u);
+            __syncthreads();
+            tile = s_tile;
+            __syncthreads();
+            if (tile >= n_tiles) break;
+        } else {
+            tile = xcd_tile(blockIdx.x, gridDim.x);
+        }
+        const int64_t r = tile * blockDim.x + threadIdx.x;
+        const bool inr = r < rs.n;
+        int f = 0;
+        Ray ray;
+        FwdResult fr;
+        bool valid = false;
+        double lval = 0.0;
+        PoseAcc pa = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+        if (inr) {
+            f = frame_of(rs.off, rs.F, r);
+            setup_ray(g, rs, op, r, f, ray);
+            float Y[9];
+            sh9(ray.d[0], ray.d[1], ray.d[2], Y);
+            ray_forward(g, op, ray, Y, fr);
+            const float z = fr.D / ray.s;
+            if (rgb_out) {
+                rgb_out[3 * r] = fr.C[0];
+                rgb_out[3 * r + 1] = fr.C[1];
+                rgb_out[3 * r + 2] = fr.C[2];
+            }
+            if (depth_out) depth_out[r] = z;
+            // Eq. 4, 5, 11; invalid depth drops the ray (Sec. 6.1)
+            const float Dt = tgt_depth[r];
+            valid = isfinite(Dt) && Dt > 0.f;
+            if (valid) {
+                const float wf = fw[f];
+                const float e0 = fr.C[0] - tgt_rgb[3 * r];
+                const float e1 = fr.C[1] - tgt_rgb[3 * r + 1];
+                const float e2 = fr.C[2] - tgt_rgb[3 * r + 2];
+                const float ed = z - Dt;
+                float rho, drho;
+                if (op.depth_loss == LOSS_L2) { rho = ed * ed; drho = 2.f * ed; }
+                else { rho = fabsf(ed); drho = ed > 0.f ? 1.f : (ed < 0.f ? -1.f : 0.f); }
+                lval = (double)wf * ((double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2)
+                     + (double)op.lambda_d * wf * rho;
+                const float gC[3] = {2.f * wf * e0, 2.f * wf * e1, 2.f * wf * e2};
+                const float gDr = op.lambda_d * wf * drho / ray.s;
+                if (GRID || POSE)
+                    ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, fr.n, fr.C, fr.D, gC, gDr, grad, pa);
+            }
+        }
+        if (loss) {
+            double lv[1] = {lval};
+            seg_sum_atomic<1>(f, valid, lv, loss);
+        }
+        if (POSE) {
+            double six[6] = {0, 0, 0, 0, 0, 0};
+            if (valid) pose_six<VIEW>(ray, pa, six);
+            seg_sum_atomic<6>(f, valid, six, grad_pose);
+        }
+        if (stats) {
+            long long sv[4] = {inr ? fr.occ : 0, inr ? fr.occ_corners : 0,
+                               valid ? fr.grad_corners : 0, valid ? 1 : 0};
+            add_stats(inr, sv, stats);
+        }
+        if (!persistent) break;
+    }
+    if (persistent && threadIdx.x == 0) {
+        // the last workgroup to finish re-arms the queue for the next launch
+        __threadfence();
+        const unsigned prev = atomicAdd(ws + 1, 1u);
+        if (prev == gridDim.x - 1) {
+            atomicExch(ws, 0u);
+            atomicExch(ws + 1, 0u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n, int block) {
+    return (unsigned)((n + block - 1) / block);
+}
+
+hipError_t launch_forward(const KGrid& g, const KRays& rs, const KOpts& op, float* rgb,
+                          float* depth, int32_t* nsamp, hipStream_t st) {
+    hipLaunchKernelGGL(k_forward, dim3(blocks_for(rs.n, 256)), dim3(256), 0, st, g, rs, op, rgb,
+                       depth, nsamp);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, const float* rgb,
+                           const float* depth, const int32_t* nsamp, const float* g_rgb,
+                           const float* g_depth, float* grad_data, double* grad_pose,
+                           hipStream_t st) {
+    const dim3 grid(blocks_for(rs.n, 256)), block(256);
+    const bool view = (op.flags & 1) != 0;
+    if (grad_data && !grad_pose) {
+        hipLaunchKernelGGL((k_backward<true, false, false>), grid, block, 0, st, g, rs, op, rgb,
+                           depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
+    } else if (!grad_data && grad_pose) {
+        if (view)
+            hipLaunchKernelGGL((k_backward<false, true, true>), grid, block, 0, st, g, rs, op, rgb,
+                               depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
+        else
+            hipLaunchKernelGGL((k_backward<false, true, false>), grid, block, 0, st, g, rs, op, rgb,
+                               depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+template <bool GRID, bool POSE, bool VIEW>
+static void fused_go(dim3 grid, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
+                     const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
+                     const float* fw, float* rgb, float* depth, double* loss, float* grad,
+                     double* gp, int64_t* stats, unsigned* ws, int persistent) {
+    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW>), grid, block, 0, st, g, rs, op, tgt_rgb,
+                       tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent);
+}
+
+hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,
+                        const float* tgt_depth, const float* frame_weight, int want, float* rgb,
+                        float* depth, double* loss, float* grad_data, double* grad_pose,
+                        int64_t* stats, unsigned* ws, int block, int variant, hipStream_t st) {
+    const int64_t tiles = (rs.n + block - 1) / block;
+    unsigned nblk = (unsigned)tiles;
+    if (variant == 1) {
+        static int cus = device_cus();
+        const int64_t cap = (int64_t)cus * (2048 / block);   // 8 waves per SIMD-set worth
+        nblk = (unsigned)(tiles < cap ? tiles : cap);
+    }
+    const dim3 grid(nblk), blk(block);
+    const bool G = want & 1, P = want & 2, V = (op.flags & 1) != 0;
+    int64_t* sp = (want & 4) ? stats : nullptr;
+    if (G && P) {
+        if (V) fused_go<true, true, true>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+        else fused_go<true, true, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+    } else if (G) {
+        fused_go<true, false, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+    } else if (P) {
+        if (V) fused_go<false, true, true>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+        else fused_go<false, true, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+    } else {
+        fused_go<false, false, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pxm

@@ -1,0 +1,339 @@
+"""Python binding of libpxm (ctypes over the C ABI in include/pxm.h).
+
+Argument marshalling only: every step of rendering and differentiation runs in
+the HIP kernels of libpxm.so.  torch supplies device memory and the current
+stream.  If the library is missing it is built once with hipcc; if that is not
+possible every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpxm.so")
+REC = 28
+
+COLOR_RELU_SHIFT, COLOR_SIGMOID, COLOR_IDENTITY = 0, 1, 2
+DEPTH_L1, DEPTH_L2 = 0, 1
+FLAG_POSE_VIEWDIR = 1
+WANT_GRID, WANT_POSE, WANT_STATS = 1, 2, 4
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "device error",
+          4: "workspace too small"}
+
+
+class PxmError(RuntimeError):
+    def __init__(self, fn, status, detail):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class _Grid(C.Structure):
+    _fields_ = [("reso", C.c_int32 * 3), ("aabb_min", C.c_float * 3), ("voxel_size", C.c_float),
+                ("link", C.c_void_p), ("n_alloc", C.c_int64), ("data", C.c_void_p)]
+
+
+class _Rays(C.Structure):
+    _fields_ = [("n_frames", C.c_int32), ("c2w", C.c_void_p), ("intr", C.c_void_p),
+                ("n_rays", C.c_int64), ("frame_offsets", C.c_void_p), ("pix", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("step_vox", C.c_float), ("max_samples", C.c_int32), ("t_near", C.c_float),
+                ("t_stop", C.c_float), ("color_act", C.c_int32), ("depth_loss", C.c_int32),
+                ("lambda_depth", C.c_float), ("flags", C.c_int32)]
+
+
+_lib = None
+_lock = threading.Lock()
+EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
+           "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_workspace_bytes",
+           "pxm_set_tuning", "pxm_get_tuning", "pxm_status_string", "pxm_last_error",
+           "pxm_abi_version")
+
+
+def lib():
+    """Load libpxm.so (building it once with hipcc if it is absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build()
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, f32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
+        G, R, O = C.POINTER(_Grid), C.POINTER(_Rays), C.POINTER(_Opts)
+        L.pxm_render_forward.argtypes = [G, R, O, P, P, P, P]
+        L.pxm_render_backward_grid.argtypes = [G, R, O, P, P, P, P, P, P, P]
+        L.pxm_render_backward_pose.argtypes = [G, R, O, P, P, P, P, P, P, P]
+        L.pxm_tv_grad.argtypes = [G, f32, f32, f32, P, P]
+        L.pxm_render_fused.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P, sz, P]
+        L.pxm_pose_adam.argtypes = [i32, P, P, P, f32, f32, f32, f32, P]
+        L.pxm_workspace_bytes.argtypes = [G, R, O, i32]
+        L.pxm_workspace_bytes.restype = sz
+        L.pxm_set_tuning.argtypes = [i32, i32]
+        L.pxm_get_tuning.argtypes = [C.POINTER(i32), C.POINTER(i32)]
+        L.pxm_get_tuning.restype = None
+        L.pxm_status_string.argtypes = [C.c_int]
+        L.pxm_status_string.restype = C.c_char_p
+        L.pxm_last_error.restype = C.c_char_p
+        for name in ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
+                     "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_set_tuning"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(fn, status):
+    if status != 0:
+        raise PxmError(fn, status, lib().pxm_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    return t
+
+
+# ----------------------------------------------------------------------------
+# device-resident inputs
+# ----------------------------------------------------------------------------
+
+@dataclass
+class DeviceGrid:
+    reso: tuple
+    aabb_min: tuple
+    voxel_size: float
+    link: torch.Tensor      # int32 [Rx*Ry*Rz]
+    data: torch.Tensor      # float32 [n_alloc, 28]
+
+    @property
+    def n_alloc(self):
+        return int(self.data.shape[0])
+
+    def struct(self, data=None) -> _Grid:
+        d = self.data if data is None else data
+        _need(self.link, "grid.link", torch.int32, (int(np.prod(self.reso)),))
+        _need(d, "grid.data", torch.float32, (self.n_alloc, REC))
+        g = _Grid()
+        g.reso[:] = [int(x) for x in self.reso]
+        g.aabb_min[:] = [float(x) for x in self.aabb_min]
+        g.voxel_size = float(self.voxel_size)
+        g.link = self.link.data_ptr()
+        g.n_alloc = self.n_alloc
+        g.data = d.data_ptr()
+        return g
+
+
+@dataclass
+class DeviceRays:
+    c2w: torch.Tensor            # float32 [F, 3, 4]
+    intr: torch.Tensor           # float32 [F, 4]
+    frame_offsets: torch.Tensor  # int32 [F+1]
+    pix: torch.Tensor            # int32 [n_rays, 2]
+    offsets_host: np.ndarray = None
+
+    @property
+    def n_frames(self):
+        return int(self.c2w.shape[0])
+
+    @property
+    def n_rays(self):
+        return int(self.pix.shape[0])
+
+    def struct(self) -> _Rays:
+        F = self.n_frames
+        _need(self.c2w, "rays.c2w", torch.float32, (F, 3, 4))
+        _need(self.intr, "rays.intr", torch.float32, (F, 4))
+        _need(self.frame_offsets, "rays.frame_offsets", torch.int32, (F + 1,))
+        _need(self.pix, "rays.pix", torch.int32, (self.n_rays, 2))
+        r = _Rays()
+        r.n_frames = F
+        r.c2w = self.c2w.data_ptr()
+        r.intr = self.intr.data_ptr()
+        r.n_rays = self.n_rays
+        r.frame_offsets = self.frame_offsets.data_ptr()
+        r.pix = self.pix.data_ptr()
+        return r
+
+
+def opts_struct(o) -> _Opts:
+    s = _Opts()
+    s.step_vox = float(o.step_vox)
+    s.max_samples = int(o.max_samples)
+    s.t_near = float(o.t_near)
+    s.t_stop = float(o.t_stop)
+    s.color_act = int(o.color_act)
+    s.depth_loss = int(o.depth_loss)
+    s.lambda_depth = float(o.lambda_depth)
+    s.flags = int(o.flags)
+    return s
+
+
+def grid_to_device(grid, device="cuda") -> DeviceGrid:
+    return DeviceGrid(tuple(int(r) for r in grid.reso), tuple(float(x) for x in grid.aabb_min),
+                      float(grid.voxel_size),
+                      torch.from_numpy(np.ascontiguousarray(grid.link, np.int32)).to(device),
+                      torch.from_numpy(np.ascontiguousarray(grid.data, np.float32)).to(device))
+
+
+def rays_to_device(rays, device="cuda") -> DeviceRays:
+    off = np.ascontiguousarray(rays.frame_offsets, np.int32)
+    return DeviceRays(torch.from_numpy(np.ascontiguousarray(rays.c2w, np.float32)).to(device),
+                      torch.from_numpy(np.ascontiguousarray(rays.intr, np.float32)).to(device),
+                      torch.from_numpy(off).to(device),
+                      torch.from_numpy(np.ascontiguousarray(rays.pix, np.int32)).to(device),
+                      off.copy())
+
+
+# ----------------------------------------------------------------------------
+# entry points (same names as the C ABI without the pxm_ prefix)
+# ----------------------------------------------------------------------------
+
+def render_forward(grid: DeviceGrid, rays: DeviceRays, opts, rgb=None, depth=None, nsamp=None,
+                   stream=None):
+    n = rays.n_rays
+    dev = grid.data.device
+    rgb = torch.empty(n, 3, device=dev) if rgb is None else _need(rgb, "rgb", torch.float32, (n, 3))
+    depth = torch.empty(n, device=dev) if depth is None else _need(depth, "depth", torch.float32, (n,))
+    nsamp = (torch.empty(n, dtype=torch.int32, device=dev) if nsamp is None
+             else _need(nsamp, "nsamp", torch.int32, (n,)))
+    g, r, o = grid.struct(), rays.struct(), opts_struct(opts)
+    _check("render_forward", lib().pxm_render_forward(C.byref(g), C.byref(r), C.byref(o), _ptr(rgb),
+                                                      _ptr(depth), _ptr(nsamp), _stream(stream)))
+    return rgb, depth, nsamp
+
+
+def _bwd_inputs(rays, rgb, depth, nsamp, g_rgb, g_depth):
+    n = rays.n_rays
+    _need(rgb, "rgb", torch.float32, (n, 3))
+    _need(depth, "depth", torch.float32, (n,))
+    _need(nsamp, "nsamp", torch.int32, (n,))
+    _need(g_rgb, "g_rgb", torch.float32, (n, 3))
+    _need(g_depth, "g_depth", torch.float32, (n,))
+
+
+def render_backward_grid(grid, rays, opts, rgb, depth, nsamp, g_rgb, g_depth, grad_data=None,
+                         stream=None):
+    _bwd_inputs(rays, rgb, depth, nsamp, g_rgb, g_depth)
+    if grad_data is None:
+        grad_data = torch.zeros_like(grid.data)
+    _need(grad_data, "grad_data", torch.float32, tuple(grid.data.shape))
+    g, r, o = grid.struct(), rays.struct(), opts_struct(opts)
+    _check("render_backward_grid", lib().pxm_render_backward_grid(
+        C.byref(g), C.byref(r), C.byref(o), _ptr(rgb), _ptr(depth), _ptr(nsamp), _ptr(g_rgb),
+        _ptr(g_depth), _ptr(grad_data), _stream(stream)))
+    return grad_data
+
+
+def render_backward_pose(grid, rays, opts, rgb, depth, nsamp, g_rgb, g_depth, grad_pose=None,
+                         stream=None):
+    _bwd_inputs(rays, rgb, depth, nsamp, g_rgb, g_depth)
+    if grad_pose is None:
+        grad_pose = torch.zeros(rays.n_frames, 6, dtype=torch.float64, device=grid.data.device)
+    _need(grad_pose, "grad_pose", torch.float64, (rays.n_frames, 6))
+    g, r, o = grid.struct(), rays.struct(), opts_struct(opts)
+    _check("render_backward_pose", lib().pxm_render_backward_pose(
+        C.byref(g), C.byref(r), C.byref(o), _ptr(rgb), _ptr(depth), _ptr(nsamp), _ptr(g_rgb),
+        _ptr(g_depth), _ptr(grad_pose), _stream(stream)))
+    return grad_pose
+
+
+def tv_grad(grid, lambda_density, lambda_sh, eps, grad_data=None, stream=None):
+    if grad_data is None:
+        grad_data = torch.zeros_like(grid.data)
+    _need(grad_data, "grad_data", torch.float32, tuple(grid.data.shape))
+    g = grid.struct()
+    _check("tv_grad", lib().pxm_tv_grad(C.byref(g), float(lambda_density), float(lambda_sh),
+                                        float(eps), _ptr(grad_data), _stream(stream)))
+    return grad_data
+
+
+def workspace_bytes(grid, rays, opts, want) -> int:
+    g, r, o = grid.struct(), rays.struct(), opts_struct(opts)
+    return int(lib().pxm_workspace_bytes(C.byref(g), C.byref(r), C.byref(o), int(want)))
+
+
+def new_workspace(grid, rays, opts, want):
+    """Zeroed workspace for render_fused (the kernel leaves it zeroed again)."""
+    nb = workspace_bytes(grid, rays, opts, want)
+    return torch.zeros((nb + 7) // 8, dtype=torch.int64, device=grid.data.device)
+
+
+def render_fused(grid, rays, opts, tgt_rgb, tgt_depth, frame_weight, want, rgb=None, depth=None,
+                 loss=None, grad_data=None, grad_pose=None, stats=None, ws=None, stream=None):
+    n, F = rays.n_rays, rays.n_frames
+    _need(tgt_rgb, "tgt_rgb", torch.float32, (n, 3))
+    _need(tgt_depth, "tgt_depth", torch.float32, (n,))
+    _need(frame_weight, "frame_weight", torch.float32, (F,))
+    if rgb is not None:
+        _need(rgb, "rgb", torch.float32, (n, 3))
+    if depth is not None:
+        _need(depth, "depth", torch.float32, (n,))
+    if loss is not None:
+        _need(loss, "loss", torch.float64, (F,))
+    if grad_data is not None:
+        _need(grad_data, "grad_data", torch.float32, tuple(grid.data.shape))
+    if grad_pose is not None:
+        _need(grad_pose, "grad_pose", torch.float64, (F, 6))
+    if stats is not None:
+        _need(stats, "stats", torch.int64, (4,))
+    if ws is None:
+        ws = new_workspace(grid, rays, opts, want)
+    g, r, o = grid.struct(), rays.struct(), opts_struct(opts)
+    _check("render_fused", lib().pxm_render_fused(
+        C.byref(g), C.byref(r), C.byref(o), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(frame_weight),
+        int(want), _ptr(rgb), _ptr(depth), _ptr(loss), _ptr(grad_data), _ptr(grad_pose),
+        _ptr(stats), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return dict(rgb=rgb, depth=depth, loss=loss, grad_data=grad_data, grad_pose=grad_pose,
+                stats=stats)
+
+
+def pose_adam(c2w, grad_pose, state, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    F = int(c2w.shape[0])
+    _need(c2w, "c2w", torch.float32, (F, 3, 4))
+    _need(grad_pose, "grad_pose", torch.float64, (F, 6))
+    _need(state, "state", torch.float64, (F, 16))
+    _check("pose_adam", lib().pxm_pose_adam(F, _ptr(c2w), _ptr(grad_pose), _ptr(state), float(lr),
+                                            float(beta1), float(beta2), float(eps),
+                                            _stream(stream)))
+
+
+def set_tuning(block: int, variant: int):
+    _check("set_tuning", lib().pxm_set_tuning(int(block), int(variant)))
+
+
+def get_tuning():
+    b, v = C.c_int32(), C.c_int32()
+    lib().pxm_get_tuning(C.byref(b), C.byref(v))
+    return int(b.value), int(v.value)
+
+
+def abi_version() -> int:
+    return int(lib().pxm_abi_version())

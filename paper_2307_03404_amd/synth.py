@@ -75,12 +75,17 @@ class Targets:
     frame_weight: np.ndarray  # f32[F] loss weight of each frame's rays (1/M)
 
 
+def f32(x) -> float:
+    """Round to the nearest float32 so both consumers see identical scalars."""
+    return float(np.float32(x))
+
+
 @dataclass
 class Opts:
     step_vox: float = 0.5
     max_samples: int = 2**31 - 1
     t_near: float = 0.0
-    t_stop: float = 1e-6
+    t_stop: float = f32(1e-6)
     color_act: int = COLOR_RELU_SHIFT
     depth_loss: int = DEPTH_L1
     lambda_depth: float = 1.0
@@ -325,13 +330,13 @@ def grid_from_mask(reso, aabb_min, vs, mask_flat, sigma_vals, rng) -> Grid:
     idx = np.flatnonzero(mask_flat)
     link[idx] = np.arange(idx.size, dtype=np.int32)
     data = _fill_payload(idx.size, rng, sigma_vals)
-    return Grid(tuple(int(r) for r in reso), np.asarray(aabb_min, np.float32), float(vs), link, data)
+    return Grid(tuple(int(r) for r in reso), np.asarray(aabb_min, np.float32), f32(vs), link, data)
 
 
 def sphere_grid(cfg: int = 1, R: int = 32) -> tuple:
     """Dense R^3 grid on [-1,1]^3; sigma = relu(N(0,1)) inside 3 spheres."""
     rng = _rng(cfg, 0)
-    vs = 2.0 / (R - 1)
+    vs = f32(2.0 / (R - 1))
     cen = rng.uniform(-0.6, 0.6, size=(3, 3))
     rad = rng.uniform(0.15, 0.4, size=3)
     i = np.arange(R)
@@ -354,7 +359,7 @@ def room_grid(cfg: int, R: int, extent: float, occupancy: float) -> tuple:
     that the allocated fraction equals ``occupancy``.
     """
     rng = _rng(cfg, 0)
-    vs = extent / R
+    vs = f32(extent / R)
     aabb_min = np.zeros(3)
     inset = 8 * vs
     top = (R - 1) * vs
@@ -392,10 +397,13 @@ def room_grid(cfg: int, R: int, extent: float, occupancy: float) -> tuple:
     return grid, scene
 
 
-def _room_camera(rng, R, vs, clearance_vox=32, pitch_deg=15.0):
+def _room_camera(rng, R, vs, scene=None, clearance_vox=32, pitch_deg=15.0):
     lo = (8 + clearance_vox) * vs
     hi = (R - 1 - 8 - clearance_vox) * vs
-    eye = rng.uniform(lo, hi, size=3)
+    for _ in range(1000):
+        eye = rng.uniform(lo, hi, size=3)
+        if scene is None or scene_distance(scene, eye[None])[0] >= clearance_vox * vs:
+            break
     yaw = rng.uniform(0, 2 * np.pi)
     pitch = np.deg2rad(rng.uniform(-pitch_deg, pitch_deg))
     fwd = np.array([np.cos(pitch) * np.cos(yaw), np.cos(pitch) * np.sin(yaw), np.sin(pitch)])
@@ -432,7 +440,7 @@ def config1() -> Workload:
     rgb, depth = sensor_targets(scene, rays, _rng(1, 3), depth_noise=0.01, missing=0.05,
                                 n_nonfinite=8)
     tg = Targets(rgb, depth, frame_weights(depth, rays.frame_offsets, False))
-    opts = Opts(step_vox=0.5, max_samples=128, t_near=0.0, t_stop=1e-6,
+    opts = Opts(step_vox=0.5, max_samples=128, t_near=0.0, t_stop=f32(1e-6),
                 color_act=COLOR_RELU_SHIFT, depth_loss=DEPTH_L1, lambda_depth=1.0)
     return Workload("c1_dense32_64x64", grid, rays, tg, opts, meta={"scene": scene})
 
@@ -441,11 +449,11 @@ def config2() -> Workload:
     """Sparse 256^3 room (~10 % allocated), one 1200x680 frame, mapping + TV."""
     grid, scene = room_grid(2, 256, 5.12, 0.10)
     rng = _rng(2, 1)
-    c2w = _room_camera(rng, 256, grid.voxel_size)
+    c2w = _room_camera(rng, 256, grid.voxel_size, scene)
     rays = _pack([c2w], [INTR_FULL], [tile_order(W_FULL, H_FULL)])
     rgb, depth = sensor_targets(scene, rays, _rng(2, 3), depth_noise=0.01, missing=0.0)
     tg = Targets(rgb, depth, frame_weights(depth, rays.frame_offsets, False))
-    opts = Opts(step_vox=0.5, t_stop=1e-6, depth_loss=DEPTH_L1)
+    opts = Opts(step_vox=0.5, depth_loss=DEPTH_L1)
     return Workload("c2_room256_1200x680_mapping", grid, rays, tg, opts,
                     meta={"scene": scene, "tv": (1e-5, 1e-6, 1e-9)})
 
@@ -476,7 +484,7 @@ def config3(grid_scene=None) -> Workload:
     rgb, depth = sensor_targets(scene_bg, rays_true, _rng(3, 3))
     rays = dataclasses.replace(rays_true, c2w=np.asarray(start, np.float32))
     tg = Targets(rgb, depth, frame_weights(depth, rays.frame_offsets, True))
-    opts = Opts(step_vox=0.5, max_samples=128, t_stop=1e-6, depth_loss=DEPTH_L1)
+    opts = Opts(step_vox=0.5, max_samples=128, depth_loss=DEPTH_L1)
     return Workload("c3_track32_16frames", grid, rays, tg, opts,
                     true_c2w=np.asarray(true, np.float32), meta={"scene": scene})
 
@@ -494,12 +502,12 @@ def config4() -> Workload:
     """Sparse 512^3 room (~3 %), 8 keyframes x 1200x680, fused mapping."""
     grid, scene = room512()
     rng = _rng(4, 1)
-    c2ws = [_room_camera(rng, 512, grid.voxel_size) for _ in range(8)]
+    c2ws = [_room_camera(rng, 512, grid.voxel_size, scene) for _ in range(8)]
     full = tile_order(W_FULL, H_FULL)
     rays = _pack(c2ws, [INTR_FULL] * 8, [full] * 8)
     rgb, depth = sensor_targets(scene, rays, _rng(4, 3), depth_noise=0.01, missing=0.05)
     tg = Targets(rgb, depth, frame_weights(depth, rays.frame_offsets, False))
-    opts = Opts(step_vox=0.5, t_stop=1e-6, depth_loss=DEPTH_L1)
+    opts = Opts(step_vox=0.5, depth_loss=DEPTH_L1)
     return Workload("c4_room512_8x1200x680_mapping", grid, rays, tg, opts, meta={"scene": scene})
 
 
@@ -511,12 +519,12 @@ def config5() -> Workload:
     c2ws, pix = [], []
     counts = rng.integers(1000, 200001, size=64)
     for f in range(64):
-        c2ws.append(_room_camera(rng, 512, grid.voxel_size))
+        c2ws.append(_room_camera(rng, 512, grid.voxel_size, scene))
         pix.append(subsample_pixels(W_FULL, H_FULL, int(counts[f]), rsub))
     rays = _pack(c2ws, [INTR_FULL] * 64, pix)
     rgb, depth = sensor_targets(scene, rays, _rng(5, 3), depth_noise=0.01, missing=0.05)
     tg = Targets(rgb, depth, frame_weights(depth, rays.frame_offsets, True))
-    opts = Opts(step_vox=0.5, t_stop=1e-6, depth_loss=DEPTH_L1)
+    opts = Opts(step_vox=0.5, depth_loss=DEPTH_L1)
     return Workload("c5_room512_64frames_mixed", grid, rays, tg, opts, meta={"scene": scene})
 
 

@@ -1,0 +1,163 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host (before anything touches a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2307_03404_amd import pxm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pxm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pxm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pxm.lib()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(pxm.EXPORTS) == set(names)
+    assert pxm.abi_version() == 1
+
+
+def test_status_strings():
+    L = pxm.lib()
+    assert L.pxm_status_string(0) == b"ok"
+    assert L.pxm_status_string(4) == b"workspace too small"
+    assert L.pxm_status_string(99) == b"unknown status"
+
+
+FAKE = 0x10000   # never dereferenced: every call below fails validation first
+
+
+def good_grid():
+    g = pxm._Grid()
+    g.reso[:] = [8, 8, 8]
+    g.aabb_min[:] = [0.0, 0.0, 0.0]
+    g.voxel_size = 0.1
+    g.link = FAKE
+    g.n_alloc = 10
+    g.data = FAKE
+    return g
+
+
+def good_rays(n=5):
+    r = pxm._Rays()
+    r.n_frames = 1
+    r.c2w = FAKE
+    r.intr = FAKE
+    r.n_rays = n
+    r.frame_offsets = FAKE
+    r.pix = FAKE
+    return r
+
+
+def good_opts():
+    o = pxm._Opts()
+    o.step_vox = 0.5
+    o.max_samples = 128
+    o.t_near = 0.0
+    o.t_stop = 1e-6
+    o.color_act = 0
+    o.depth_loss = 0
+    o.lambda_depth = 1.0
+    o.flags = 0
+    return o
+
+
+def fwd(g, r, o, outs=(FAKE, FAKE, FAKE)):
+    return pxm.lib().pxm_render_forward(C.byref(g) if g is not None else None,
+                                        C.byref(r) if r is not None else None,
+                                        C.byref(o) if o is not None else None, *outs, None)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda g, r, o: g.reso.__setitem__(1, 1), 2),
+    (lambda g, r, o: setattr(g, "voxel_size", 0.0), 1),
+    (lambda g, r, o: setattr(g, "voxel_size", float("nan")), 1),
+    (lambda g, r, o: g.aabb_min.__setitem__(0, float("inf")), 1),
+    (lambda g, r, o: setattr(g, "link", None), 1),
+    (lambda g, r, o: setattr(g, "data", FAKE + 4), 1),
+    (lambda g, r, o: setattr(g, "n_alloc", -1), 1),
+    (lambda g, r, o: setattr(r, "n_frames", 0), 1),
+    (lambda g, r, o: setattr(r, "n_rays", -3), 1),
+    (lambda g, r, o: setattr(r, "pix", None), 1),
+    (lambda g, r, o: setattr(o, "step_vox", 0.0), 1),
+    (lambda g, r, o: setattr(o, "step_vox", float("inf")), 1),
+    (lambda g, r, o: setattr(o, "max_samples", 0), 1),
+    (lambda g, r, o: setattr(o, "t_stop", 1.0), 1),
+    (lambda g, r, o: setattr(o, "t_stop", -0.1), 1),
+    (lambda g, r, o: setattr(o, "t_near", -1.0), 1),
+    (lambda g, r, o: setattr(o, "color_act", 3), 1),
+    (lambda g, r, o: setattr(o, "depth_loss", 2), 1),
+    (lambda g, r, o: setattr(o, "flags", 8), 1),
+])
+def test_forward_rejects_bad_arguments(mutate, code):
+    g, r, o = good_grid(), good_rays(), good_opts()
+    mutate(g, r, o)
+    assert fwd(g, r, o) == code
+    assert pxm.lib().pxm_last_error()
+
+
+def test_null_descriptors_and_outputs():
+    assert fwd(None, good_rays(), good_opts()) == 1
+    assert fwd(good_grid(), None, good_opts()) == 1
+    assert fwd(good_grid(), good_rays(), None) == 1
+    assert fwd(good_grid(), good_rays(), good_opts(), (FAKE, None, FAKE)) == 1
+
+
+def test_zero_rays_is_a_noop():
+    assert fwd(good_grid(), good_rays(0), good_opts()) == 0
+
+
+def test_backward_and_fused_argument_checks():
+    L = pxm.lib()
+    g, r, o = good_grid(), good_rays(), good_opts()
+    args = [C.byref(g), C.byref(r), C.byref(o)]
+    assert L.pxm_render_backward_grid(*args, FAKE, FAKE, FAKE, FAKE, FAKE, None, None) == 1
+    assert L.pxm_render_backward_pose(*args, FAKE, FAKE, FAKE, None, FAKE, FAKE, None) == 1
+    # fused: unknown want bit, missing grad buffers, small workspace
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 8, None, None, None, None, None, None,
+                              FAKE, 4096, None) == 1
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 1, None, None, None, None, None, None,
+                              FAKE, 4096, None) == 1
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 2, None, None, None, None, None, None,
+                              FAKE, 4096, None) == 1
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 0, None, None, None, None, None, None,
+                              FAKE, 8, None) == 4
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 0, None, None, None, None, None, None,
+                              None, 4096, None) == 1
+    assert L.pxm_workspace_bytes(*args, 3) >= 8
+
+
+def test_tv_adam_and_tuning_checks():
+    L = pxm.lib()
+    g = good_grid()
+    assert L.pxm_tv_grad(C.byref(g), 1.0, 1.0, 0.0, FAKE, None) == 1
+    assert L.pxm_tv_grad(C.byref(g), float("nan"), 1.0, 1e-9, FAKE, None) == 1
+    assert L.pxm_tv_grad(C.byref(g), 1.0, 1.0, 1e-9, None, None) == 1
+    assert L.pxm_pose_adam(0, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.999, 1e-8, None) == 1
+    assert L.pxm_pose_adam(2, FAKE, FAKE, FAKE, 1e-3, 1.0, 0.999, 1e-8, None) == 1
+    assert L.pxm_pose_adam(2, FAKE, FAKE, None, 1e-3, 0.9, 0.999, 1e-8, None) == 1
+    assert L.pxm_set_tuning(100, 0) == 1
+    assert L.pxm_set_tuning(256, 2) == 1
+    before = pxm.get_tuning()
+    pxm.set_tuning(128, 1)
+    assert pxm.get_tuning() == (128, 1)
+    pxm.set_tuning(*before)
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    grid = pxm.DeviceGrid((2, 2, 2), (0, 0, 0), 1.0, torch.zeros(8, dtype=torch.int32),
+                          torch.zeros(1, 28))
+    with pytest.raises(ValueError):
+        grid.struct()
