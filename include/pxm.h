@@ -205,7 +205,7 @@ size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm
 
 /*
  * Launch tuning for pxm_render_fused (process-wide; read at each call):
- *   block    rays per workgroup (64, 128, 256 or 512; 0 = default 256)
+ *   block    rays per workgroup (64, 128 or 256; 0 = default 256)
  *   variant  0 = one workgroup per ray tile, 1 = persistent workgroups
  *            pulling ray tiles from a device counter in the workspace
  * Returns PXM_INVALID_ARGUMENT for values outside these sets.

@@ -1,0 +1,211 @@
+"""Batching around the fused kernel: ray packer, autotuner, captured tracking loop.
+
+* pack_frames: many frames with uneven ray counts -> one CSR ray batch whose
+  rays are ordered in 8x8 pixel tiles inside each frame (one 64-lane wave per
+  tile), plus the permutation back to the caller's order.
+* Autotuner: times pxm_render_fused over launch shapes (rays per workgroup x
+  plain/persistent tile queue) on the real inputs and caches the winner per
+  problem signature in a JSON file.  Run it before any graph capture.
+* TrackingGraph: `iters` tracking iterations (fused forward + loss + pose
+  backward for every frame, then the Adam pose update) captured once into a
+  HIP graph and replayed without host round trips (Sec. 5.3-5.4).
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import pxm
+
+
+def tile_sort(pix: np.ndarray, width: int, tile: int = 8) -> np.ndarray:
+    """Permutation putting pixels (u, v) in tile-major order (tiles row-major,
+    pixels row-major inside a tile)."""
+    pix = np.asarray(pix)
+    u, v = pix[:, 0].astype(np.int64), pix[:, 1].astype(np.int64)
+    tiles_x = (width + tile - 1) // tile
+    key = ((v // tile) * tiles_x + (u // tile)) * tile * tile + (v % tile) * tile + (u % tile)
+    return np.argsort(key, kind="stable")
+
+
+@dataclass
+class PackedRays:
+    c2w: np.ndarray            # f32 [F, 3, 4]
+    intr: np.ndarray           # f32 [F, 4]
+    frame_offsets: np.ndarray  # i32 [F + 1]
+    pix: np.ndarray            # i32 [n, 2]
+    order: np.ndarray          # i64 [n]: packed ray j is input ray order[j]
+
+    @property
+    def n_frames(self):
+        return int(self.c2w.shape[0])
+
+    @property
+    def n_rays(self):
+        return int(self.pix.shape[0])
+
+
+def pack_frames(frames, width: int, tile: int = 8) -> PackedRays:
+    """frames: iterable of (c2w [3,4], intr [4], pix [n_f, 2]).  Rays keep their
+    frame grouping (CSR); inside a frame they are reordered into pixel tiles."""
+    c2w, intr, pix, order, counts = [], [], [], [], []
+    base = 0
+    for m, k, p in frames:
+        p = np.asarray(p, np.int32).reshape(-1, 2)
+        perm = tile_sort(p, width, tile)
+        c2w.append(np.asarray(m, np.float32).reshape(3, 4))
+        intr.append(np.asarray(k, np.float32).reshape(4))
+        pix.append(p[perm])
+        order.append(base + perm)
+        counts.append(p.shape[0])
+        base += p.shape[0]
+    off = np.zeros(len(counts) + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    if off[-1] > np.iinfo(np.int32).max:
+        raise ValueError("too many rays for int32 CSR offsets")
+    return PackedRays(np.stack(c2w), np.stack(intr), off.astype(np.int32),
+                      np.concatenate(pix) if pix else np.zeros((0, 2), np.int32),
+                      np.concatenate(order) if order else np.zeros(0, np.int64))
+
+
+# ----------------------------------------------------------------------------
+# autotuner
+# ----------------------------------------------------------------------------
+
+CANDIDATES = [(b, v) for b in (64, 128, 256) for v in (0, 1)]
+
+
+def _signature(grid, rays, opts, want) -> str:
+    return "r%s_n%d_rays%d_f%d_w%d_fl%d_act%d" % (
+        "x".join(str(int(x)) for x in grid.reso), grid.n_alloc, rays.n_rays, rays.n_frames,
+        int(want), int(opts.flags), int(opts.color_act))
+
+
+class Autotuner:
+    """Chooses pxm_set_tuning(block, variant) for pxm_render_fused by timing."""
+
+    def __init__(self, cache_path: str | None = None, reps: int = 5, warmup: int = 2):
+        self.cache_path = cache_path or os.path.join(
+            os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "pxm", "tune.json")
+        self.reps, self.warmup = reps, warmup
+        self.cache = {}
+        if os.path.exists(self.cache_path):
+            try:
+                with open(self.cache_path) as fh:
+                    self.cache = json.load(fh)
+            except (OSError, ValueError):
+                self.cache = {}
+
+    def _save(self):
+        try:
+            os.makedirs(os.path.dirname(self.cache_path), exist_ok=True)
+            tmp = self.cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(self.cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, self.cache_path)
+        except OSError:
+            pass
+
+    def tune(self, grid, rays, opts, tgt_rgb, tgt_depth, frame_weight, want, grad_data=None,
+             grad_pose=None, force=False):
+        """Returns ((block, variant), {candidate: ms}) and applies the winner."""
+        sig = _signature(grid, rays, opts, want)
+        if not force and sig in self.cache:
+            b, v = self.cache[sig]["best"]
+            pxm.set_tuning(b, v)
+            return (b, v), self.cache[sig]["ms"]
+        dev = grid.data.device
+        if grad_data is None and want & pxm.WANT_GRID:
+            grad_data = torch.zeros_like(grid.data)
+        if grad_pose is None and want & pxm.WANT_POSE:
+            grad_pose = torch.zeros(rays.n_frames, 6, dtype=torch.float64, device=dev)
+        ws = pxm.new_workspace(grid, rays, opts, want)
+        results = {}
+        old = pxm.get_tuning()
+        try:
+            for b, v in CANDIDATES:
+                pxm.set_tuning(b, v)
+                call = lambda: pxm.render_fused(grid, rays, opts, tgt_rgb, tgt_depth, frame_weight,
+                                                want, grad_data=grad_data, grad_pose=grad_pose,
+                                                ws=ws)
+                for _ in range(self.warmup):
+                    call()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(self.reps):
+                    call()
+                e1.record()
+                torch.cuda.synchronize()
+                results["%d/%d" % (b, v)] = e0.elapsed_time(e1) / self.reps
+        finally:
+            pxm.set_tuning(*old)
+        best = min(results, key=results.get)
+        b, v = (int(x) for x in best.split("/"))
+        pxm.set_tuning(b, v)
+        self.cache[sig] = {"best": [b, v], "ms": results, "time": time.time()}
+        self._save()
+        return (b, v), results
+
+
+# ----------------------------------------------------------------------------
+# captured tracking loop
+# ----------------------------------------------------------------------------
+
+class TrackingGraph:
+    """`iters` tracking iterations for all frames of `rays`, captured once.
+
+    Each iteration: fused forward + loss + pose backward (PXM_WANT_POSE) into
+    grad_pose, then pxm_pose_adam, which updates rays.c2w in place and zeroes
+    grad_pose.  losses[it, f] holds the loss of frame f before update it.
+    """
+
+    def __init__(self, grid, rays, opts, tgt_rgb, tgt_depth, frame_weight, iters=20, lr=1e-3,
+                 betas=(0.9, 0.999), eps=1e-8):
+        dev = grid.data.device
+        F = rays.n_frames
+        self.grid, self.rays, self.opts = grid, rays, opts
+        self.tgt = (tgt_rgb, tgt_depth, frame_weight)
+        self.iters, self.lr, self.betas, self.eps = iters, lr, betas, eps
+        self.grad_pose = torch.zeros(F, 6, dtype=torch.float64, device=dev)
+        self.state = torch.zeros(F, 16, dtype=torch.float64, device=dev)
+        self.losses = torch.zeros(iters, F, dtype=torch.float64, device=dev)
+        self.ws = pxm.new_workspace(grid, rays, opts, pxm.WANT_POSE)
+        self.graph = None
+
+    def _body(self):
+        self.grad_pose.zero_()
+        self.losses.zero_()
+        for it in range(self.iters):
+            pxm.render_fused(self.grid, self.rays, self.opts, *self.tgt, pxm.WANT_POSE,
+                             loss=self.losses[it], grad_pose=self.grad_pose, ws=self.ws)
+            pxm.pose_adam(self.rays.c2w, self.grad_pose, self.state, self.lr, self.betas[0],
+                          self.betas[1], self.eps)
+
+    def run_eager(self):
+        self._body()
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):          # warm-up outside the capture
+            pass
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._body()
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def reset(self, c2w: torch.Tensor):
+        """Restore the starting poses and clear the optimiser state."""
+        self.rays.c2w.copy_(c2w)
+        self.state.zero_()

@@ -141,8 +141,8 @@ const char* pxm_status_string(int s) {
 
 int pxm_set_tuning(int32_t block, int32_t variant) {
     if (block == 0) block = 256;
-    if (block != 64 && block != 128 && block != 256 && block != 512)
-        return fail(PXM_INVALID_ARGUMENT, "block = %d not in {64,128,256,512}", block);
+    if (block != 64 && block != 128 && block != 256)
+        return fail(PXM_INVALID_ARGUMENT, "block = %d not in {64,128,256}", block);
     if (variant != 0 && variant != 1) return fail(PXM_INVALID_ARGUMENT, "variant = %d not in {0,1}", variant);
     g_block.store(block);
     g_variant.store(variant);

@@ -10,6 +10,7 @@
 // forward's nsamp positions, re-deriving sigma, c, w and T_{i+1} (nothing is
 // stored per sample), and scatter or reduce the gradients.
 #include "internal.hpp"
+#include "scatter.hpp"
 
 namespace pxm {
 
@@ -82,11 +83,14 @@ struct PoseAcc {
 // Backward march of one ray over its first n kept positions (Eq. 6-14).
 //   Chat, Dhat: the forward's colour and expected range
 //   gC, gDr:    dL/dC-hat and dL/d(range)
+// Wave-synchronous: every lane of the wave must call it (lanes without a ray
+// pass n = 0), because the grid scatter merges lanes step by step.
 template <bool GRID, bool POSE, bool VIEW>
 __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, const Ray& ray,
                                              const float Y[9], int n, const float Chat[3],
                                              float Dhat, const float gC[3], float gDr,
-                                             float* __restrict__ grad, PoseAcc& pa) {
+                                             float* __restrict__ grad, const WaveCache& wc,
+                                             PoseAcc& pa) {
     float GY[9][3];
     if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
     float A0 = 0.f, A1 = 0.f, A2 = 0.f, AD = 0.f, T = 1.f;
@@ -94,122 +98,122 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
     const float delta = op.step_vox;
     const float inv_vs = (float)g.inv_vs;
     int64_t k = ray.k_first;
-    for (int i = 0; i < n; ++i, ++k) {
-        Sample s;
-        if (!sample_at(g, ray, k, s)) break;
+    for (int i = 0;; ++i, ++k) {
+        bool run = i < n;
+        if (__ballot(run) == 0) break;
+        bool have = false;
+        int64_t key = -1;
         int idx[8];
-        if (load_links(g, s.base, idx) == 0) continue;
-        CornerVals cv;
-        float ev[8][3][3];      // per corner, channel: sum_k dY_k/dd * SH_k (VIEW only)
-        if (VIEW) {
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                cv.sig[b] = 0.f;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    cv.e[b][c] = 0.f;
-                    ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
-                }
-                if (idx[b] >= 0) {
-                    float rec[REC];
-                    load_record(g.data, idx[b], rec);
-                    cv.sig[b] = rec[0];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-                        for (int kk = 0; kk < 9; ++kk) {
-                            const float sh = rec[1 + 9 * c + kk];
-                            acc = fmaf(Y[kk], sh, acc);
-                            a0 = fmaf(GY[kk][0], sh, a0);
-                            a1 = fmaf(GY[kk][1], sh, a1);
-                            a2 = fmaf(GY[kk][2], sh, a2);
-                        }
-                        cv.e[b][c] = acc;
-                        ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
-                    }
-                }
-            }
-        } else {
-            load_corner_vals(g, idx, Y, cv);
-        }
         float w[8];
-        trilinear_weights(s.f, w);
-        float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
+        float gsig = 0.f, gs[3] = {0.f, 0.f, 0.f};
+        if (run) {
+            Sample s;
+            if (!sample_at(g, ray, k, s)) {
+                n = i;          // left the box: nothing further on this ray
+            } else if (load_links(g, s.base, idx) > 0) {
+                CornerVals cv;
+                float ev[8][3][3];      // per corner, channel: sum_k dY_k/dd * SH_k (VIEW only)
+                if (VIEW) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            sr = fmaf(w[b], cv.sig[b], sr);
+                    for (int b = 0; b < 8; ++b) {
+                        cv.sig[b] = 0.f;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
-        }
-        if (!(sr > 0.f)) continue;      // sigma = 0: no light, zero gradient (ReLU)
-        const float x = sr * delta;
-        const float wt = T * (-expm1f(-x));
-        L += (double)x;
-        const float Tn = trans_of(L);
-        float c[3], gs[3];
+                        for (int c = 0; c < 3; ++c) {
+                            cv.e[b][c] = 0.f;
+                            ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
+                        }
+                        if (idx[b] >= 0) {
+                            float rec[REC];
+                            load_record(g.data, idx[b], rec);
+                            cv.sig[b] = rec[0];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            c[ch] = act_fwd(op.act, sc[ch]);
-            gs[ch] = act_bwd(op.act, sc[ch]) * wt * gC[ch];      // Eq. 8 through act
-        }
-        A0 = fmaf(wt, c[0], A0);
-        A1 = fmaf(wt, c[1], A1);
-        A2 = fmaf(wt, c[2], A2);
-        AD = fmaf(wt, s.t, AD);
-        // Eq. 9 and Eq. 10 with inclusive prefixes A = sum_{j<=i} c_j w_j
-        const float gsig = delta * (gC[0] * (c[0] * Tn - Chat[0] + A0)
+                            for (int c = 0; c < 3; ++c) {
+                                float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+                                for (int kk = 0; kk < 9; ++kk) {
+                                    const float sh = rec[1 + 9 * c + kk];
+                                    acc = fmaf(Y[kk], sh, acc);
+                                    a0 = fmaf(GY[kk][0], sh, a0);
+                                    a1 = fmaf(GY[kk][1], sh, a1);
+                                    a2 = fmaf(GY[kk][2], sh, a2);
+                                }
+                                cv.e[b][c] = acc;
+                                ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
+                            }
+                        }
+                    }
+                } else {
+                    load_corner_vals(g, idx, Y, cv);
+                }
+                trilinear_weights(s.f, w);
+                float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    sr = fmaf(w[b], cv.sig[b], sr);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
+                }
+                if (sr > 0.f) {         // sigma = 0: no light, zero gradient (ReLU)
+                    const float x = sr * delta;
+                    const float wt = T * (-expm1f(-x));
+                    L += (double)x;
+                    const float Tn = trans_of(L);
+                    float c[3];
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        c[ch] = act_fwd(op.act, sc[ch]);
+                        gs[ch] = act_bwd(op.act, sc[ch]) * wt * gC[ch];      // Eq. 8 through act
+                    }
+                    A0 = fmaf(wt, c[0], A0);
+                    A1 = fmaf(wt, c[1], A1);
+                    A2 = fmaf(wt, c[2], A2);
+                    AD = fmaf(wt, s.t, AD);
+                    // Eq. 9 and Eq. 10 with inclusive prefixes A = sum_{j<=i} c_j w_j
+                    gsig = delta * (gC[0] * (c[0] * Tn - Chat[0] + A0)
                                   + gC[1] * (c[1] * Tn - Chat[1] + A1)
                                   + gC[2] * (c[2] * Tn - Chat[2] + A2)
                                   + gDr * (s.t * Tn - Dhat + AD));
-        if (GRID) {
+                    have = true;
+                    key = s.base;
+                    if (POSE) {
+                        // Appendix A: grad of the interpolant = sum_b grad(w_b) v_b; fold
+                        // the sample's upstream gradients into one value per corner.
+                        float h[8];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                if (idx[b] < 0) continue;
-                float* __restrict__ p = grad + (int64_t)idx[b] * REC;
-                unsafeAtomicAdd(p, w[b] * gsig);
+                        for (int b = 0; b < 8; ++b)
+                            h[b] = gsig * cv.sig[b] + gs[0] * cv.e[b][0] + gs[1] * cv.e[b][1]
+                                 + gs[2] * cv.e[b][2];
+                        const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
+                        const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
+                        const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
+                                       + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
+                        const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
+                                       + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
+                        const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
+                                       + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
+                        const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const float gb = w[b] * gs[ch];
+                        for (int a = 0; a < 3; ++a) {
+                            pa.go[a] += gp[a];
+                            pa.gd[a] = fmaf(s.t, gp[a], pa.gd[a]);
+                        }
+                        if (VIEW) {
 #pragma unroll
-                    for (int kk = 0; kk < 9; ++kk) unsafeAtomicAdd(p + 1 + 9 * ch + kk, gb * Y[kk]);
+                            for (int a = 0; a < 3; ++a) {
+                                float acc = 0.f;
+#pragma unroll
+                                for (int b = 0; b < 8; ++b)
+                                    acc = fmaf(w[b], gs[0] * ev[b][0][a] + gs[1] * ev[b][1][a]
+                                                         + gs[2] * ev[b][2][a], acc);
+                                pa.gv[a] += acc;
+                            }
+                        }
+                    }
+                    T = Tn;
                 }
             }
         }
-        if (POSE) {
-            // Appendix A: grad of the interpolant = sum_b grad(w_b) v_b; fold the
-            // sample's upstream gradients into one value per corner first.
-            float h[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                h[b] = gsig * cv.sig[b] + gs[0] * cv.e[b][0] + gs[1] * cv.e[b][1] + gs[2] * cv.e[b][2];
-            const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
-            const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
-            // d/dfx: (h[1jk] - h[0jk]) weighted by wy_j wz_k, etc.
-            const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
-                           + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
-            const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
-                           + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
-            const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
-                           + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
-            const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                pa.go[a] += gp[a];
-                pa.gd[a] = fmaf(s.t, gp[a], pa.gd[a]);
-            }
-            if (VIEW) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int b = 0; b < 8; ++b)
-                        acc = fmaf(w[b], gs[0] * ev[b][0][a] + gs[1] * ev[b][1][a] + gs[2] * ev[b][2][a], acc);
-                    pa.gv[a] += acc;
-                }
-            }
-        }
-        T = Tn;
+        if (GRID) scatter_merged(have, key, idx, w, gsig, gs, Y, wc, grad);
     }
 }
 
@@ -259,26 +263,43 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
                                                   const float* __restrict__ g_depth,
                                                   float* __restrict__ grad,
                                                   double* __restrict__ grad_pose) {
+    extern __shared__ float smem[];
+    WaveCache wc{nullptr, nullptr};
+    if (GRID) {
+        wc = wave_cache(smem);
+        cache_init(wc);
+        __syncthreads();
+    }
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = r < rs.n;
     int f = 0;
     Ray ray;
     PoseAcc pa = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float Y[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float gC[3] = {0.f, 0.f, 0.f}, Chat[3] = {0.f, 0.f, 0.f};
+    float gDr = 0.f, Dhat = 0.f;
+    int n = 0;
+    ray.empty = true;
     if (active) {
-        const float gC[3] = {g_rgb[3 * r], g_rgb[3 * r + 1], g_rgb[3 * r + 2]};
+        gC[0] = g_rgb[3 * r];
+        gC[1] = g_rgb[3 * r + 1];
+        gC[2] = g_rgb[3 * r + 2];
         const float gD = g_depth[r];
         active = gC[0] != 0.f || gC[1] != 0.f || gC[2] != 0.f || gD != 0.f;
         if (active) {
             f = frame_of(rs.off, rs.F, r);
             setup_ray(g, rs, op, r, f, ray);
-            float Y[9];
             sh9(ray.d[0], ray.d[1], ray.d[2], Y);
-            const float Chat[3] = {rgb[3 * r], rgb[3 * r + 1], rgb[3 * r + 2]};
-            const float Dhat = depth[r] * ray.s;
-            ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, nsamp[r], Chat, Dhat, gC, gD / ray.s,
-                                           grad, pa);
+            Chat[0] = rgb[3 * r];
+            Chat[1] = rgb[3 * r + 1];
+            Chat[2] = rgb[3 * r + 2];
+            Dhat = depth[r] * ray.s;
+            gDr = gD / ray.s;
+            n = ray.empty ? 0 : nsamp[r];
         }
     }
+    ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, n, Chat, Dhat, gC, gDr, grad, wc, pa);
+    if (GRID) cache_flush(wc, grad);
     if (POSE) {
         double six[6] = {0, 0, 0, 0, 0, 0};
         if (active) pose_six<VIEW>(ray, pa, six);
@@ -297,7 +318,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
 }
 
 template <bool GRID, bool POSE, bool VIEW>
-__global__ void __launch_bounds__(512) k_fused(KGrid g, KRays rs, KOpts op,
+__global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
                                                const float* __restrict__ tgt_rgb,
                                                const float* __restrict__ tgt_depth,
                                                const float* __restrict__ fw,
@@ -309,6 +330,13 @@ __global__ void __launch_bounds__(512) k_fused(KGrid g, KRays rs, KOpts op,
                                                int64_t* __restrict__ stats,
                                                unsigned* __restrict__ ws, int persistent) {
     __shared__ int64_t s_tile;
+    extern __shared__ float smem[];
+    WaveCache wc{nullptr, nullptr};
+    if (GRID) {
+        wc = wave_cache(smem);
+        cache_init(wc);
+        __syncthreads();
+    }
     const int64_t n_tiles = (rs.n + blockDim.x - 1) / blockDim.x;
     for (;;) {
         int64_t tile;
@@ -325,14 +353,18 @@ __global__ void __launch_bounds__(512) k_fused(KGrid g, KRays rs, KOpts op,
         const bool inr = r < rs.n;
         int f = 0;
         Ray ray;
+        ray.empty = true;
         FwdResult fr;
         bool valid = false;
         double lval = 0.0;
         PoseAcc pa = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+        float Y[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float gC[3] = {0.f, 0.f, 0.f};
+        float gDr = 0.f;
+        int nb = 0;
         if (inr) {
             f = frame_of(rs.off, rs.F, r);
             setup_ray(g, rs, op, r, f, ray);
-            float Y[9];
             sh9(ray.d[0], ray.d[1], ray.d[2], Y);
             ray_forward(g, op, ray, Y, fr);
             const float z = fr.D / ray.s;
@@ -356,12 +388,17 @@ __global__ void __launch_bounds__(512) k_fused(KGrid g, KRays rs, KOpts op,
                 else { rho = fabsf(ed); drho = ed > 0.f ? 1.f : (ed < 0.f ? -1.f : 0.f); }
                 lval = (double)wf * ((double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2)
                      + (double)op.lambda_d * wf * rho;
-                const float gC[3] = {2.f * wf * e0, 2.f * wf * e1, 2.f * wf * e2};
-                const float gDr = op.lambda_d * wf * drho / ray.s;
-                if (GRID || POSE)
-                    ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, fr.n, fr.C, fr.D, gC, gDr, grad, pa);
+                gC[0] = 2.f * wf * e0;
+                gC[1] = 2.f * wf * e1;
+                gC[2] = 2.f * wf * e2;
+                gDr = op.lambda_d * wf * drho / ray.s;
+                nb = fr.n;
             }
+        } else {
+            fr.C[0] = fr.C[1] = fr.C[2] = fr.D = 0.f;
         }
+        if (GRID || POSE)
+            ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, nb, fr.C, fr.D, gC, gDr, grad, wc, pa);
         if (loss) {
             double lv[1] = {lval};
             seg_sum_atomic<1>(f, valid, lv, loss);
@@ -378,6 +415,7 @@ __global__ void __launch_bounds__(512) k_fused(KGrid g, KRays rs, KOpts op,
         }
         if (!persistent) break;
     }
+    if (GRID) cache_flush(wc, grad);
     if (persistent && threadIdx.x == 0) {
         // the last workgroup to finish re-arms the queue for the next launch
         __threadfence();
@@ -411,7 +449,8 @@ hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, con
     const dim3 grid(blocks_for(rs.n, 256)), block(256);
     const bool view = (op.flags & 1) != 0;
     if (grad_data && !grad_pose) {
-        hipLaunchKernelGGL((k_backward<true, false, false>), grid, block, 0, st, g, rs, op, rgb,
+        const size_t lds = (256 / WAVE) * CACHE_FLOATS * sizeof(float);
+        hipLaunchKernelGGL((k_backward<true, false, false>), grid, block, lds, st, g, rs, op, rgb,
                            depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
     } else if (!grad_data && grad_pose) {
         if (view)
@@ -439,7 +478,8 @@ static void fused_go(dim3 grid, dim3 block, hipStream_t st, const KGrid& g, cons
                      const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                      const float* fw, float* rgb, float* depth, double* loss, float* grad,
                      double* gp, int64_t* stats, unsigned* ws, int persistent) {
-    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW>), grid, block, 0, st, g, rs, op, tgt_rgb,
+    const size_t lds = GRID ? (block.x / WAVE) * CACHE_FLOATS * sizeof(float) : 0;
+    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW>), grid, block, lds, st, g, rs, op, tgt_rgb,
                        tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent);
 }
 
