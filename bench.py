@@ -69,6 +69,68 @@ def cpu_baseline(wl, budget_s=15.0):
                       f"backward in FP64, {dt:.1f} s"}
 
 
+def compare_per_frame(wl, g, r, trgb, tdep, fw, steps, warmup):
+    """Batched fused launch over all frames vs. the same work issued frame by
+    frame: (a) one fused launch per frame, (b) the unfused kernels per frame
+    (forward, loss gradient in torch, grid backward, pose backward)."""
+    import torch
+    from paper_2307_03404_amd import pxm
+    n, F = wl.rays.n_rays, wl.rays.n_frames
+    off = wl.rays.frame_offsets
+    dev = g.data.device
+    gd = torch.zeros_like(g.data)
+    gp = torch.zeros(F, 6, dtype=torch.float64, device=dev)
+    loss = torch.zeros(F, dtype=torch.float64, device=dev)
+    want = pxm.WANT_GRID | pxm.WANT_POSE
+    frames = []
+    for f in range(F):
+        a, b = int(off[f]), int(off[f + 1])
+        rf = pxm.DeviceRays(r.c2w[f:f + 1], r.intr[f:f + 1],
+                            torch.tensor([0, b - a], dtype=torch.int32, device=dev), r.pix[a:b])
+        frames.append((a, b, rf))
+
+    def batched():
+        pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, want, loss=loss, grad_data=gd, grad_pose=gp)
+
+    def per_frame_fused():
+        for f, (a, b, rf) in enumerate(frames):
+            pxm.render_fused(g, rf, wl.opts, trgb[a:b], tdep[a:b], fw[f:f + 1], want,
+                             loss=loss[f:f + 1], grad_data=gd, grad_pose=gp[f:f + 1])
+
+    lam = float(wl.opts.lambda_depth)
+
+    def per_frame_unfused():
+        for f, (a, b, rf) in enumerate(frames):
+            rgb, depth, ns = pxm.render_forward(g, rf, wl.opts)
+            t = tdep[a:b]
+            valid = torch.isfinite(t) & (t > 0)
+            g_rgb = torch.where(valid[:, None], 2.0 * fw[f] * (rgb - trgb[a:b]), 0.0).contiguous()
+            g_dep = torch.where(valid, lam * fw[f] * torch.sign(depth - torch.where(valid, t, 0.0)),
+                                0.0).contiguous()
+            pxm.render_backward_grid(g, rf, wl.opts, rgb, depth, ns, g_rgb, g_dep, gd)
+            pxm.render_backward_pose(g, rf, wl.opts, rgb, depth, ns, g_rgb, g_dep, gp[f:f + 1])
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tb, tf, tu = timed(batched), timed(per_frame_fused), timed(per_frame_unfused)
+    return {"metric": "batched fused fwd+bwd vs per-frame launches (speedup, rays/s ratio)",
+            "value": tu / tb, "unit": "x", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": tb * 1e3, "higher_is_better": True, "scaling": "strong",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "rays": n, "frames": F},
+            "batched_rays_per_s": n / tb, "per_frame_fused_rays_per_s": n / tf,
+            "per_frame_unfused_rays_per_s": n / tu, "speedup_vs_per_frame_fused": tf / tb,
+            "speedup_vs_per_frame_unfused": tu / tb}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +141,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--compare-per-frame", action="store_true",
+                    help="time one batched fused launch against per-frame launches instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -103,8 +167,21 @@ def main():
     n, F = wl.rays.n_rays, wl.rays.n_frames
     want = pxm.WANT_GRID | pxm.WANT_POSE
     tv = wl.meta.get("tv", (1e-5, 1e-6, 1e-9))
+    if args.compare_per_frame:
+        print(json.dumps(compare_per_frame(wl, g, r, trgb, tdep, fw, args.steps, args.warmup)),
+              flush=True)
+        return
+    tuned_ms = None
     if args.block or args.variant >= 0:
         pxm.set_tuning(args.block or 256, max(args.variant, 0))
+    else:
+        from paper_2307_03404_amd.batch import Autotuner
+        cache = os.path.join(ROOT, "gpurun_out", "tune.json") if os.path.isdir(
+            os.path.join(ROOT, "gpurun_out")) else None
+        (b_, v_), tuned_ms = Autotuner(cache, reps=3, warmup=1).tune(
+            g, r, wl.opts, trgb, tdep, fw, pxm.WANT_GRID | pxm.WANT_POSE, force=True)
+        log("autotuned launch shape: %d rays/workgroup, variant %d (%s)" % (
+            b_, v_, ", ".join("%s: %.2f ms" % kv for kv in sorted(tuned_ms.items()))))
     block, variant = pxm.get_tuning()
 
     rgb = torch.empty(n, 3, device=dev)
@@ -187,6 +264,7 @@ def main():
                      "kernel": "k_fused<true,true,false>", "kernel_ms": fused_ms,
                      "alg_bytes_per_launch": bytes_launch},
         "kernels_ms": {"fused": fused_ms, "tv": tv_ms},
+        "autotune_ms": tuned_ms,
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample ...")

@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define PXM_ABI_VERSION 1
+#define PXM_ABI_VERSION 2
 #define PXM_RECORD 28          /* floats per vertex: density + 3 x 9 SH */
 
 typedef enum {
@@ -87,6 +87,9 @@ typedef struct {
     const int32_t *link;    /* [Rx*Ry*Rz], index (x*Ry + y)*Rz + z -> record id or -1 */
     int64_t n_alloc;        /* number of records */
     const float *data;      /* [n_alloc][28], 16-byte aligned */
+    const uint32_t *occ;    /* optional occupancy bitfield from pxm_build_occupancy for THIS
+                               link table, or NULL.  Lets the march step over empty cells and
+                               8^3-cell bricks; results are identical with or without it. */
 } pxm_grid;
 
 typedef struct {
@@ -198,6 +201,18 @@ int pxm_render_fused(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts 
  */
 int pxm_pose_adam(int32_t n_frames, float *c2w, double *grad_pose, double *state, float lr,
                   float beta1, float beta2, float eps, void *stream);
+
+/*
+ * Occupancy bitfield for empty-space skipping (an exact acceleration: a cell
+ * whose 8 corners are all empty interpolates to zero density and carries no
+ * light or gradient).  Level 0 holds one bit per cell ((x*(Ry-1)+y)*W0 + z/32,
+ * W0 = ceil((Rz-1)/32)), level 1 one bit per brick of 8^3 cells.  Build it on
+ * `stream` from grid->link / grid->n_alloc (grid->data and grid->occ are not
+ * read) into `occ` of n_words >= pxm_occupancy_words(grid) uint32 words, and
+ * rebuild it whenever the link table changes.
+ */
+size_t pxm_occupancy_words(const pxm_grid *grid);
+int pxm_build_occupancy(const pxm_grid *grid, uint32_t *occ, size_t n_words, void *stream);
 
 /* Workspace bytes pxm_render_fused needs for these arguments and `want`. */
 size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,

@@ -54,8 +54,7 @@ def render(grid: "pxm.DeviceGrid", rays: "pxm.DeviceRays", opts, data=None, xi=N
     elif xi.requires_grad and bool((xi.detach() != 0).any()):
         raise ValueError("xi is a tangent at the current pose and must be zero; "
                          "apply the update to rays.c2w instead")
-    g = grid if data is grid.data else pxm.DeviceGrid(grid.reso, grid.aabb_min, grid.voxel_size,
-                                                     grid.link, data.detach())
+    g = grid if data is grid.data else grid.with_data(data.detach())
     return RenderFunction.apply(data, xi, g, rays, opts)
 
 
@@ -63,6 +62,5 @@ def tv_loss_grad(grid, data, lambda_density, lambda_sh, eps=1e-9):
     """Adds the TV gradient into data.grad (allocating it if needed)."""
     if data.grad is None:
         data.grad = torch.zeros_like(data)
-    pxm.tv_grad(pxm.DeviceGrid(grid.reso, grid.aabb_min, grid.voxel_size, grid.link, data.detach()),
-                lambda_density, lambda_sh, eps, data.grad)
+    pxm.tv_grad(grid.with_data(data.detach()), lambda_density, lambda_sh, eps, data.grad)
     return data.grad

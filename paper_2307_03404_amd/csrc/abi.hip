@@ -81,6 +81,10 @@ pxm::KGrid kgrid(const pxm_grid* g) {
     k.n_alloc = g->n_alloc;
     k.link = g->link;
     k.data = g->data;
+    int64_t w0, w1;
+    pxm::occ_layout(g->reso, w0, k.W0, k.B, w1);
+    k.occ0 = g->occ;
+    k.occ1 = g->occ ? g->occ + w0 : nullptr;
     return k;
 }
 
@@ -208,6 +212,24 @@ int pxm_tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, flo
         return fail(PXM_INVALID_ARGUMENT, "grad_data must be 16-byte aligned");
     return launched(pxm::launch_tv(kgrid(grid), lambda_density, lambda_sh, eps, grad_data,
                                    (hipStream_t)stream), "tv_grad");
+}
+
+size_t pxm_occupancy_words(const pxm_grid* grid) {
+    if (check_grid(grid, false) != PXM_OK) return 0;
+    int64_t w0, w1;
+    int W0, B[3];
+    pxm::occ_layout(grid->reso, w0, W0, B, w1);
+    return (size_t)(w0 + w1);
+}
+
+int pxm_build_occupancy(const pxm_grid* grid, uint32_t* occ, size_t n_words, void* stream) {
+    PXM_TRY(check_grid(grid, false));
+    if (!occ) return fail(PXM_INVALID_ARGUMENT, "occ is NULL");
+    const size_t need = pxm_occupancy_words(grid);
+    if (n_words < need) return fail(PXM_WORKSPACE_TOO_SMALL, "occ has %zu < %zu words", n_words, need);
+    pxm::KGrid k = kgrid(grid);
+    k.occ0 = k.occ1 = nullptr;
+    return launched(pxm::launch_occupancy(k, occ, (hipStream_t)stream), "build_occupancy");
 }
 
 size_t pxm_workspace_bytes(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,

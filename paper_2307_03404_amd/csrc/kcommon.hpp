@@ -37,6 +37,11 @@ struct KGrid {
     int64_t n_alloc;
     const int32_t* __restrict__ link;
     const float* __restrict__ data;
+    // optional occupancy bitfield (see occ.hip); occ0 == nullptr disables skipping
+    const uint32_t* __restrict__ occ0;   // one bit per cell, rows along z
+    const uint32_t* __restrict__ occ1;   // one bit per 8^3-cell brick
+    int W0;                              // level-0 words per (x, y) cell row
+    int B[3];                            // bricks per axis
 };
 
 struct KRays {
@@ -271,6 +276,7 @@ __device__ __forceinline__ void setup_ray(const KGrid& g, const KRays& rs, const
 
 struct Sample {
     int64_t base;       // link index of the cell's (0,0,0) corner
+    int c[3];           // cell coordinates
     float f[3];         // in-cell fractions
     float t;            // distance from the camera centre (world)
 };
@@ -288,8 +294,43 @@ __device__ __forceinline__ bool sample_at(const KGrid& g, const Ray& ray, int64_
     s.f[1] = (float)(q1 - (double)c1);
     s.f[2] = (float)(q2 - (double)c2);
     s.base = (int64_t)c0 * g.sx + (int64_t)c1 * g.sy + c2;
+    s.c[0] = c0; s.c[1] = c1; s.c[2] = c2;
     s.t = ray.t0 + (float)k * ray.dw;
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// empty-space skipping with the occupancy bitfield
+// ---------------------------------------------------------------------------
+
+// A cell is occupied iff one of its 8 corners is allocated.
+__device__ __forceinline__ bool cell_occupied(const KGrid& g, const int c[3]) {
+    const uint32_t w = g.occ0[((int64_t)c[0] * (g.R[1] - 1) + c[1]) * g.W0 + (c[2] >> 5)];
+    return (w >> (c[2] & 31)) & 1u;
+}
+
+__device__ __forceinline__ bool brick_empty(const KGrid& g, const int c[3]) {
+    const int64_t b = ((int64_t)(c[0] >> 3) * g.B[1] + (c[1] >> 3)) * g.B[2] + (c[2] >> 3);
+    return !((g.occ1[b >> 5] >> (b & 31)) & 1u);
+}
+
+// For sample k lying in an empty brick: the first sample index after k that is
+// not guaranteed to lie inside the brick.  Every index in (k, result) has its
+// position inside [8b, min(8b + 8, R - 1)) shrunk by 1e-6 voxel on each axis,
+// hence in one of the brick's (empty) cells and inside the box.
+__device__ __forceinline__ int64_t brick_exit(const KGrid& g, const Ray& ray, int64_t k,
+                                              const int c[3]) {
+    double kx = 1.0e300;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double lo = (double)(8 * (c[a] >> 3));
+        const double hi = fmin(lo + 8.0, (double)(g.R[a] - 1));
+        if (ray.st[a] > 0.0) kx = fmin(kx, (hi - 1e-6 - ray.b[a]) / ray.st[a]);
+        else if (ray.st[a] < 0.0) kx = fmin(kx, (lo + 1e-6 - ray.b[a]) / ray.st[a]);
+    }
+    if (!(kx < 4.0e18)) return k + 1;
+    const int64_t nxt = (int64_t)floor(kx) + 1;
+    return nxt > k + 1 ? nxt : k + 1;
 }
 
 // Corner b = 4*i + 2*j + k  (x, y, z offsets in {0,1}).

@@ -4,9 +4,9 @@
 // orders full frames in 8x8 tiles), so the lanes gather nearly the same
 // vertices at the same sample index and share cache lines.
 //
-// Forward (Eq. 1-3): march the kept sample positions, skip cells whose 8
-// corners are all empty (exact: they interpolate to zero density) and
-// composite colour and range.  Backward (Eq. 6-14): replay exactly the
+// Forward (Eq. 1-3): march the kept sample positions, skip empty bricks and
+// cells (exact: they interpolate to zero density) and composite colour and
+// range.  Backward (Eq. 6-14): replay exactly the
 // forward's nsamp positions, re-deriving sigma, c, w and T_{i+1} (nothing is
 // stored per sample), and scatter or reduce the gradients.
 #include "internal.hpp"
@@ -23,7 +23,10 @@ struct FwdResult {
     long long grad_corners;   // allocated corners of samples with sigma_raw > 0
 };
 
-// Forward march of one ray.
+// Forward march of one ray (Eq. 1-3).  With the occupancy bitfield, samples
+// in empty bricks are stepped over in one jump and empty cells cost one bit
+// test; both are exact (such samples interpolate to zero density) and still
+// count as kept positions.
 __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, const Ray& ray,
                                             const float Y[9], FwdResult& out) {
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, T = 1.f;
@@ -32,10 +35,29 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
     long long occ = 0, occc = 0, gradc = 0;
     if (!ray.empty) {
         const float delta = op.step_vox;
-        for (int64_t k = ray.k_first; n < op.max_samples; ++k) {
+        int64_t k = ray.k_first;
+        while (n < op.max_samples) {
             Sample s;
             if (!sample_at(g, ray, k, s)) break;
+            if (g.occ0) {
+                if (brick_empty(g, s.c)) {
+                    const int64_t nxt = brick_exit(g, ray, k, s.c);
+                    if (nxt - k >= (int64_t)(op.max_samples - n)) {
+                        n = op.max_samples;
+                        break;
+                    }
+                    n += (int)(nxt - k);
+                    k = nxt;
+                    continue;
+                }
+                if (!cell_occupied(g, s.c)) {
+                    ++n;
+                    ++k;
+                    continue;
+                }
+            }
             ++n;
+            ++k;
             int idx[8];
             const int na = load_links(g, s.base, idx);
             if (na == 0) continue;
@@ -80,11 +102,140 @@ struct PoseAcc {
     float gv[3];        // dL/dd through the SH basis (optional exact term)
 };
 
+// Running state of a backward march.
+struct BwdState {
+    float A[3];         // sum_{j<=i} c_j w_j
+    float AD;           // sum_{j<=i} t_j w_j
+    float T;            // T_i
+    double L;           // sum_{j<i} sigma_j delta
+};
+
+// Backward work of one occupied sample (Eq. 6-14): updates the running state
+// and the pose accumulators; returns true with the sample's grid-gradient
+// factors (gsig = dL/d sigma_raw, gs = dL/ds_c) when it carries light.
+template <bool POSE, bool VIEW>
+__device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op, const Ray& ray,
+                                                const float Y[9], const float GY[9][3],
+                                                const Sample& s, const float Chat[3], float Dhat,
+                                                const float gC[3], float gDr, BwdState& st,
+                                                PoseAcc& pa, int idx[8], float w[8], float& gsig,
+                                                float gs[3]) {
+    if (load_links(g, s.base, idx) == 0) return false;
+    CornerVals cv;
+    float ev[8][3][3];      // per corner, channel: sum_k dY_k/dd * SH_k (VIEW only)
+    if (VIEW) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            cv.sig[b] = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cv.e[b][c] = 0.f;
+                ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
+            }
+            if (idx[b] >= 0) {
+                float rec[REC];
+                load_record(g.data, idx[b], rec);
+                cv.sig[b] = rec[0];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+                    for (int kk = 0; kk < 9; ++kk) {
+                        const float sh = rec[1 + 9 * c + kk];
+                        acc = fmaf(Y[kk], sh, acc);
+                        a0 = fmaf(GY[kk][0], sh, a0);
+                        a1 = fmaf(GY[kk][1], sh, a1);
+                        a2 = fmaf(GY[kk][2], sh, a2);
+                    }
+                    cv.e[b][c] = acc;
+                    ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
+                }
+            }
+        }
+    } else {
+        load_corner_vals(g, idx, Y, cv);
+    }
+    trilinear_weights(s.f, w);
+    float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        sr = fmaf(w[b], cv.sig[b], sr);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
+    }
+    if (!(sr > 0.f)) return false;      // sigma = 0: no light, zero gradient (ReLU)
+    const float delta = op.step_vox;
+    const float x = sr * delta;
+    const float wt = st.T * (-expm1f(-x));
+    st.L += (double)x;
+    const float Tn = trans_of(st.L);
+    float c[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        c[ch] = act_fwd(op.act, sc[ch]);
+        gs[ch] = act_bwd(op.act, sc[ch]) * wt * gC[ch];      // Eq. 8 through act
+        st.A[ch] = fmaf(wt, c[ch], st.A[ch]);
+    }
+    st.AD = fmaf(wt, s.t, st.AD);
+    // Eq. 9 and Eq. 10 with inclusive prefixes A = sum_{j<=i} c_j w_j
+    gsig = delta * (gC[0] * (c[0] * Tn - Chat[0] + st.A[0])
+                  + gC[1] * (c[1] * Tn - Chat[1] + st.A[1])
+                  + gC[2] * (c[2] * Tn - Chat[2] + st.A[2])
+                  + gDr * (s.t * Tn - Dhat + st.AD));
+    if (POSE) {
+        // Appendix A: grad of the interpolant = sum_b grad(w_b) v_b; fold the
+        // sample's upstream gradients into one value per corner first.
+        float h[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            h[b] = gsig * cv.sig[b] + gs[0] * cv.e[b][0] + gs[1] * cv.e[b][1] + gs[2] * cv.e[b][2];
+        const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
+        const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
+        const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
+                       + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
+        const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
+                       + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
+        const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
+                       + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
+        const float inv_vs = (float)g.inv_vs;
+        const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            pa.go[a] += gp[a];
+            pa.gd[a] = fmaf(s.t, gp[a], pa.gd[a]);
+        }
+        if (VIEW) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float acc = 0.f;
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    acc = fmaf(w[b], gs[0] * ev[b][0][a] + gs[1] * ev[b][1][a] + gs[2] * ev[b][2][a], acc);
+                pa.gv[a] += acc;
+            }
+        }
+    }
+    st.T = Tn;
+    return true;
+}
+
+__device__ __forceinline__ int64_t wave_min(int64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const int64_t o = __shfl_xor(v, m, WAVE);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
 // Backward march of one ray over its first n kept positions (Eq. 6-14).
 //   Chat, Dhat: the forward's colour and expected range
 //   gC, gDr:    dL/dC-hat and dL/d(range)
-// Wave-synchronous: every lane of the wave must call it (lanes without a ray
-// pass n = 0), because the grid scatter merges lanes step by step.
+// With GRID the lanes of a wave march in lockstep on the absolute sample
+// index (so that lanes of one tile share cells and their scatters merge):
+// every lane must call this (lanes without a ray pass n = 0); steps where no
+// lane has an occupied cell are jumped over together.  Without GRID every
+// lane marches on its own.
 template <bool GRID, bool POSE, bool VIEW>
 __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, const Ray& ray,
                                              const float Y[9], int n, const float Chat[3],
@@ -93,127 +244,68 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
                                              PoseAcc& pa) {
     float GY[9][3];
     if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
-    float A0 = 0.f, A1 = 0.f, A2 = 0.f, AD = 0.f, T = 1.f;
-    double L = 0.0;
-    const float delta = op.step_vox;
-    const float inv_vs = (float)g.inv_vs;
-    int64_t k = ray.k_first;
-    for (int i = 0;; ++i, ++k) {
-        bool run = i < n;
-        if (__ballot(run) == 0) break;
-        bool have = false;
-        int64_t key = -1;
-        int idx[8];
-        float w[8];
-        float gsig = 0.f, gs[3] = {0.f, 0.f, 0.f};
-        if (run) {
+    BwdState st = {{0.f, 0.f, 0.f}, 0.f, 1.f, 0.0};
+    const int64_t ks = ray.k_first, ke = ray.k_first + (n > 0 ? n : 0);
+    bool has = n > 0;
+    if (GRID) {
+        int64_t k = wave_min(has ? ks : INT64_MAX);
+        for (;;) {
+            const bool live = has && k < ke;
+            if (__ballot(live) == 0) break;
+            const bool run = live && k >= ks;
+            int64_t adv = live ? (run ? 1 : ks - k) : INT64_MAX;
+            bool work = false;
             Sample s;
-            if (!sample_at(g, ray, k, s)) {
-                n = i;          // left the box: nothing further on this ray
-            } else if (load_links(g, s.base, idx) > 0) {
-                CornerVals cv;
-                float ev[8][3][3];      // per corner, channel: sum_k dY_k/dd * SH_k (VIEW only)
-                if (VIEW) {
-#pragma unroll
-                    for (int b = 0; b < 8; ++b) {
-                        cv.sig[b] = 0.f;
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            cv.e[b][c] = 0.f;
-                            ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
-                        }
-                        if (idx[b] >= 0) {
-                            float rec[REC];
-                            load_record(g.data, idx[b], rec);
-                            cv.sig[b] = rec[0];
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-                                for (int kk = 0; kk < 9; ++kk) {
-                                    const float sh = rec[1 + 9 * c + kk];
-                                    acc = fmaf(Y[kk], sh, acc);
-                                    a0 = fmaf(GY[kk][0], sh, a0);
-                                    a1 = fmaf(GY[kk][1], sh, a1);
-                                    a2 = fmaf(GY[kk][2], sh, a2);
-                                }
-                                cv.e[b][c] = acc;
-                                ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
-                            }
-                        }
-                    }
-                } else {
-                    load_corner_vals(g, idx, Y, cv);
-                }
-                trilinear_weights(s.f, w);
-                float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    sr = fmaf(w[b], cv.sig[b], sr);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
-                }
-                if (sr > 0.f) {         // sigma = 0: no light, zero gradient (ReLU)
-                    const float x = sr * delta;
-                    const float wt = T * (-expm1f(-x));
-                    L += (double)x;
-                    const float Tn = trans_of(L);
-                    float c[3];
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) {
-                        c[ch] = act_fwd(op.act, sc[ch]);
-                        gs[ch] = act_bwd(op.act, sc[ch]) * wt * gC[ch];      // Eq. 8 through act
-                    }
-                    A0 = fmaf(wt, c[0], A0);
-                    A1 = fmaf(wt, c[1], A1);
-                    A2 = fmaf(wt, c[2], A2);
-                    AD = fmaf(wt, s.t, AD);
-                    // Eq. 9 and Eq. 10 with inclusive prefixes A = sum_{j<=i} c_j w_j
-                    gsig = delta * (gC[0] * (c[0] * Tn - Chat[0] + A0)
-                                  + gC[1] * (c[1] * Tn - Chat[1] + A1)
-                                  + gC[2] * (c[2] * Tn - Chat[2] + A2)
-                                  + gDr * (s.t * Tn - Dhat + AD));
-                    have = true;
-                    key = s.base;
-                    if (POSE) {
-                        // Appendix A: grad of the interpolant = sum_b grad(w_b) v_b; fold
-                        // the sample's upstream gradients into one value per corner.
-                        float h[8];
-#pragma unroll
-                        for (int b = 0; b < 8; ++b)
-                            h[b] = gsig * cv.sig[b] + gs[0] * cv.e[b][0] + gs[1] * cv.e[b][1]
-                                 + gs[2] * cv.e[b][2];
-                        const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
-                        const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
-                        const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
-                                       + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
-                        const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
-                                       + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
-                        const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
-                                       + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
-                        const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            pa.go[a] += gp[a];
-                            pa.gd[a] = fmaf(s.t, gp[a], pa.gd[a]);
-                        }
-                        if (VIEW) {
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                float acc = 0.f;
-#pragma unroll
-                                for (int b = 0; b < 8; ++b)
-                                    acc = fmaf(w[b], gs[0] * ev[b][0][a] + gs[1] * ev[b][1][a]
-                                                         + gs[2] * ev[b][2][a], acc);
-                                pa.gv[a] += acc;
-                            }
-                        }
-                    }
-                    T = Tn;
+            if (run) {
+                if (!sample_at(g, ray, k, s)) {
+                    has = false;            // left the box: nothing further on this ray
+                    adv = INT64_MAX;
+                } else if (g.occ0 && brick_empty(g, s.c)) {
+                    const int64_t nxt = brick_exit(g, ray, k, s.c);
+                    adv = (nxt < ke ? nxt : ke) - k;
+                } else if (!g.occ0 || cell_occupied(g, s.c)) {
+                    work = true;
                 }
             }
+            if (__ballot(work) == 0) {
+                const int64_t step = wave_min(adv);
+                if (step == INT64_MAX) break;       // every live lane has just left the box
+                k += step;
+                continue;
+            }
+            bool have = false;
+            int idx[8];
+            float w[8];
+            float gsig = 0.f, gs[3] = {0.f, 0.f, 0.f};
+            if (work)
+                have = backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
+                                                   pa, idx, w, gsig, gs);
+            scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
+            ++k;
         }
-        if (GRID) scatter_merged(have, key, idx, w, gsig, gs, Y, wc, grad);
+    } else {
+        int64_t k = ks;
+        while (k < ke) {
+            Sample s;
+            if (!sample_at(g, ray, k, s)) break;
+            if (g.occ0) {
+                if (brick_empty(g, s.c)) {
+                    const int64_t nxt = brick_exit(g, ray, k, s.c);
+                    k = nxt < ke ? nxt : ke;
+                    continue;
+                }
+                if (!cell_occupied(g, s.c)) {
+                    ++k;
+                    continue;
+                }
+            }
+            int idx[8];
+            float w[8];
+            float gsig, gs[3];
+            backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st, pa, idx, w,
+                                        gsig, gs);
+            ++k;
+        }
     }
 }
 

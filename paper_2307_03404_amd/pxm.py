@@ -36,7 +36,8 @@ class PxmError(RuntimeError):
 
 class _Grid(C.Structure):
     _fields_ = [("reso", C.c_int32 * 3), ("aabb_min", C.c_float * 3), ("voxel_size", C.c_float),
-                ("link", C.c_void_p), ("n_alloc", C.c_int64), ("data", C.c_void_p)]
+                ("link", C.c_void_p), ("n_alloc", C.c_int64), ("data", C.c_void_p),
+                ("occ", C.c_void_p)]
 
 
 class _Rays(C.Structure):
@@ -54,6 +55,7 @@ _lib = None
 _lock = threading.Lock()
 EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
            "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_workspace_bytes",
+           "pxm_occupancy_words", "pxm_build_occupancy",
            "pxm_set_tuning", "pxm_get_tuning", "pxm_status_string", "pxm_last_error",
            "pxm_abi_version")
 
@@ -78,6 +80,10 @@ def lib():
         L.pxm_tv_grad.argtypes = [G, f32, f32, f32, P, P]
         L.pxm_render_fused.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P, sz, P]
         L.pxm_pose_adam.argtypes = [i32, P, P, P, f32, f32, f32, f32, P]
+        L.pxm_occupancy_words.argtypes = [G]
+        L.pxm_occupancy_words.restype = sz
+        L.pxm_build_occupancy.argtypes = [G, P, sz, P]
+        L.pxm_build_occupancy.restype = C.c_int
         L.pxm_workspace_bytes.argtypes = [G, R, O, i32]
         L.pxm_workspace_bytes.restype = sz
         L.pxm_set_tuning.argtypes = [i32, i32]
@@ -132,6 +138,7 @@ class DeviceGrid:
     voxel_size: float
     link: torch.Tensor      # int32 [Rx*Ry*Rz]
     data: torch.Tensor      # float32 [n_alloc, 28]
+    occ: torch.Tensor = None  # int32 words of the occupancy bitfield (optional)
 
     @property
     def n_alloc(self):
@@ -148,7 +155,23 @@ class DeviceGrid:
         g.link = self.link.data_ptr()
         g.n_alloc = self.n_alloc
         g.data = d.data_ptr()
+        g.occ = self.occ.data_ptr() if self.occ is not None else None
         return g
+
+    def with_data(self, data) -> "DeviceGrid":
+        """Same structure (links, occupancy) with another payload tensor."""
+        return DeviceGrid(self.reso, self.aabb_min, self.voxel_size, self.link, data, self.occ)
+
+    def build_occupancy(self, stream=None) -> "DeviceGrid":
+        """(Re)build the occupancy bitfield from the link table."""
+        g = self.struct()
+        g.occ = None
+        n = int(lib().pxm_occupancy_words(C.byref(g)))
+        occ = torch.empty(n, dtype=torch.int32, device=self.link.device)
+        _check("build_occupancy", lib().pxm_build_occupancy(C.byref(g), _ptr(occ), n,
+                                                           _stream(stream)))
+        self.occ = occ
+        return self
 
 
 @dataclass
@@ -196,11 +219,14 @@ def opts_struct(o) -> _Opts:
     return s
 
 
-def grid_to_device(grid, device="cuda") -> DeviceGrid:
-    return DeviceGrid(tuple(int(r) for r in grid.reso), tuple(float(x) for x in grid.aabb_min),
-                      float(grid.voxel_size),
-                      torch.from_numpy(np.ascontiguousarray(grid.link, np.int32)).to(device),
-                      torch.from_numpy(np.ascontiguousarray(grid.data, np.float32)).to(device))
+def grid_to_device(grid, device="cuda", occupancy=True) -> DeviceGrid:
+    g = DeviceGrid(tuple(int(r) for r in grid.reso), tuple(float(x) for x in grid.aabb_min),
+                   float(grid.voxel_size),
+                   torch.from_numpy(np.ascontiguousarray(grid.link, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(grid.data, np.float32)).to(device))
+    if occupancy:
+        g.build_occupancy()
+    return g
 
 
 def rays_to_device(rays, device="cuda") -> DeviceRays:

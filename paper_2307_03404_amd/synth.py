@@ -386,6 +386,9 @@ def room_grid(cfg: int, R: int, extent: float, occupancy: float) -> tuple:
     for x in range(R):
         p = np.concatenate([np.full((yz.shape[0], 1), x * vs), yz], 1)
         dist[x * R * R:(x + 1) * R * R] = (scene_distance(scene, p) / vs).astype(np.float32)
+    # axis-aligned surfaces put many vertices at exactly the same distance;
+    # a tiny seeded jitter breaks those ties so the quantile hits the target
+    dist += rng.uniform(0.0, 1e-3, size=dist.size).astype(np.float32)
     sample = dist[rng.integers(0, dist.size, size=min(dist.size, 8_000_000))]
     b = float(np.quantile(sample, occupancy))
     mask = dist <= b
