@@ -280,7 +280,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             if (work)
                 have = backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
                                                    pa, idx, w, gsig, gs);
-            scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
+            scatter_merged(have, s.base, s.c, idx, w, gsig, gs, Y, wc, grad);
             ++k;
         }
     } else {
@@ -541,8 +541,10 @@ hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, con
     const dim3 grid(blocks_for(rs.n, 256)), block(256);
     const bool view = (op.flags & 1) != 0;
     if (grad_data && !grad_pose) {
-        const size_t lds = (256 / WAVE) * CACHE_FLOATS * sizeof(float);
-        hipLaunchKernelGGL((k_backward<true, false, false>), grid, block, lds, st, g, rs, op, rgb,
+        // one wave per workgroup: the per-wave LDS (cache + MFMA staging) is ~24 KB
+        const size_t lds = WAVE_LDS_FLOATS * sizeof(float);
+        hipLaunchKernelGGL((k_backward<true, false, false>), dim3(blocks_for(rs.n, WAVE)),
+                           dim3(WAVE), lds, st, g, rs, op, rgb,
                            depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
     } else if (!grad_data && grad_pose) {
         if (view)
@@ -555,6 +557,14 @@ hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, con
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+static size_t device_lds() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return (size_t)v;
 }
 
 static int device_cus() {
@@ -570,7 +580,7 @@ static void fused_go(dim3 grid, dim3 block, hipStream_t st, const KGrid& g, cons
                      const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                      const float* fw, float* rgb, float* depth, double* loss, float* grad,
                      double* gp, int64_t* stats, unsigned* ws, int persistent) {
-    const size_t lds = GRID ? (block.x / WAVE) * CACHE_FLOATS * sizeof(float) : 0;
+    const size_t lds = GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float) : 0;
     hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW>), grid, block, lds, st, g, rs, op, tgt_rgb,
                        tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent);
 }
@@ -579,6 +589,13 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
                         const float* tgt_depth, const float* frame_weight, int want, float* rgb,
                         float* depth, double* loss, float* grad_data, double* grad_pose,
                         int64_t* stats, unsigned* ws, int block, int variant, hipStream_t st) {
+    if (want & 1) {
+        // the grid scatter needs WAVE_LDS_FLOATS of LDS per wave: shrink the
+        // workgroup if the device cannot give this many waves' worth
+        static size_t max_lds = device_lds();
+        while (block > WAVE && (size_t)(block / WAVE) * WAVE_LDS_FLOATS * sizeof(float) > max_lds)
+            block /= 2;
+    }
     const int64_t tiles = (rs.n + block - 1) / block;
     unsigned nblk = (unsigned)tiles;
     if (variant == 1) {
