@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_c2_room256_816k_rays_traffic.md")
+KERNEL_SOURCES = ("include/pxm.h", "paper_2307_03404_amd/csrc")
 
 
 def log(*a):
@@ -47,6 +50,55 @@ def alg_bytes(stats, n_rays, n_frames, want):
     if want & 1:
         b += 224 * grad_c
     return b
+
+
+def sources_sha256():
+    """Digest of the kernel sources: HBM counters are only valid for the code
+    they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    files = []
+    for rel in KERNEL_SOURCES:
+        p = os.path.join(ROOT, rel)
+        if os.path.isdir(p):
+            files += sorted(os.path.join(p, f) for f in os.listdir(p)
+                            if f.endswith((".hip", ".hpp", ".h")))
+        else:
+            files.append(p)
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name, block, variant):
+    """HBM bytes per fused launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs (each scaled by the same counter's reading on a copy of known
+    size), or None when they were taken on other kernel sources, another
+    workload or another launch shape."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            kv = dict(m.groups() for m in re.finditer(r"^- (\w+): `([^`]*)`", fh.read(), re.M))
+        if (kv.get("sources_sha256") != sources_sha256() or kv.get("workload") != workload_name
+                or int(kv.get("block", -1)) != block or int(kv.get("variant", -1)) != variant):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """Plain device-to-device copies of a known size, for scaling the HBM
+    byte counters (run under rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}),
+          flush=True)
 
 
 def cpu_baseline(wl, budget_s=15.0):
@@ -143,6 +195,8 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--compare-per-frame", action="store_true",
                     help="time one batched fused launch against per-frame launches instead")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 1 GiB device copies (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -154,6 +208,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     t0 = time.perf_counter()
     wl = workload(args.workload)
@@ -242,6 +299,7 @@ def main():
     ms = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
     achieved = bytes_launch / (fused_ms * 1e-3) / 1e9
+    traffic = measured_traffic(wl.name, block, variant)
     out = {
         "metric": "fwd+bwd rays/s (mapping & tracking), 1200x680 rays, 256^3 grid; % of HBM peak",
         "value": value,
@@ -260,8 +318,10 @@ def main():
                    "step": "fused fwd+loss+grid+pose bwd, TV grad, Adam pose update",
                    "block": block, "variant": variant},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
                      "kernel": "k_fused<true,true,false>", "kernel_ms": fused_ms,
+                     "traffic_gbs": None if traffic is None else traffic / (fused_ms * 1e-3) / 1e9,
                      "alg_bytes_per_launch": bytes_launch},
         "kernels_ms": {"fused": fused_ms, "tv": tv_ms},
         "autotune_ms": tuned_ms,
