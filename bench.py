@@ -101,24 +101,100 @@ def copy_calibration(nbytes=1 << 30, reps=3):
           flush=True)
 
 
-def cpu_baseline(wl, budget_s=15.0):
-    """The FP64 oracle (forward, loss, grid + pose backward) on a bounded
+def cpu_baseline(wl, budget_s=15.0, want_grid=True):
+    """The FP64 oracle (forward, loss, grid and/or pose backward) on a bounded
     seeded ray sample of the same workload, on this host's cores."""
     import oracle
     from paper_2307_03404_amd import synth
     oracle.build() if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")) else None
     probe = synth.subset_rays(wl, 4000, seed=21)
     t0 = time.perf_counter()
-    oracle.fused(probe.grid, probe.rays, probe.targets, probe.opts)
+    oracle.fused(probe.grid, probe.rays, probe.targets, probe.opts, want_grid=want_grid)
     dt = time.perf_counter() - t0
     n = int(min(wl.rays.n_rays, max(4000, 4000 * budget_s / max(dt, 1e-3))))
     sample = synth.subset_rays(wl, n, seed=22)
     t0 = time.perf_counter()
-    oracle.fused(sample.grid, sample.rays, sample.targets, sample.opts)
+    oracle.fused(sample.grid, sample.rays, sample.targets, sample.opts, want_grid=want_grid)
     dt = time.perf_counter() - t0
+    what = "grid+pose" if want_grid else "pose"
     return {"value": n / dt, "unit": "rays/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} of {wl.rays.n_rays} rays (seeded uniform subset), fwd+loss+grid+pose "
+            "sample": f"{n} of {wl.rays.n_rays} rays (seeded uniform subset), fwd+loss+{what} "
                       f"backward in FP64, {dt:.1f} s"}
+
+
+def tracking_bench(wl, g, r, trgb, tdep, fw, args):
+    """Tracking: `iters` Adam iterations of fused forward + loss + pose
+    backward over every frame, captured in one hipGraph; one step = one
+    replay.  rays/s counts every ray of every iteration."""
+    import torch
+    from paper_2307_03404_amd import pxm
+    from paper_2307_03404_amd.batch import TrackingGraph
+    n, F = wl.rays.n_rays, wl.rays.n_frames
+    iters = int(wl.meta.get("iters", 20))
+    c2w0 = r.c2w.clone()
+    tg = TrackingGraph(g, r, wl.opts, trgb, tdep, fw, iters=iters, lr=1e-3)
+    tg.run_eager()                                   # warm-up and lazy set-up outside capture
+    torch.cuda.synchronize()
+    tg.reset(c2w0)
+    tg.capture()
+    for _ in range(args.warmup):
+        tg.reset(c2w0)
+        tg.replay()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        tg.reset(c2w0)
+        ev[i][0].record()
+        tg.replay()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    graph_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    first, last = tg.losses[0].sum().item(), tg.losses[-1].sum().item()
+    # the dominant kernel, timed alone on the same stream
+    stats = torch.zeros(4, dtype=torch.int64, device=g.data.device)
+    loss = torch.zeros(F, dtype=torch.float64, device=g.data.device)
+    gp = torch.zeros(F, 6, dtype=torch.float64, device=g.data.device)
+    ws = pxm.new_workspace(g, r, wl.opts, pxm.WANT_POSE)
+    r.c2w.copy_(c2w0)
+    pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, pxm.WANT_POSE | pxm.WANT_STATS, loss=loss,
+                     grad_pose=gp, stats=stats, ws=ws)
+    torch.cuda.synchronize()
+    bytes_launch = alg_bytes(stats.cpu().numpy(), n, F, pxm.WANT_POSE)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, pxm.WANT_POSE, loss=loss, grad_pose=gp,
+                         ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    kern_ms = e0.elapsed_time(e1) / 10
+    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+    block, variant = pxm.get_tuning()
+    out = {
+        "metric": "tracking rays/s (fwd + loss + se(3) pose bwd + Adam, all frames, "
+                  f"{iters} iterations in one hipGraph)",
+        "value": n * iters * args.steps / elapsed, "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "rays": n, "frames": F, "iters": iters,
+                   "grid": list(wl.grid.reso), "step": "one replay of the captured tracking loop",
+                   "block": block, "variant": variant},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_fused<false,true,false>", "kernel_ms": kern_ms,
+                     "alg_bytes_per_launch": bytes_launch},
+        "graph_ms_median": graph_ms,
+        "loss_first_last_iteration": [first, last],
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, want_grid=False)
+    r.c2w.copy_(c2w0)
+    return out
 
 
 def compare_per_frame(wl, g, r, trgb, tdep, fw, steps, warmup):
@@ -222,12 +298,9 @@ def main():
     tdep = torch.from_numpy(wl.targets.depth).to(dev)
     fw = torch.from_numpy(wl.targets.frame_weight).to(dev)
     n, F = wl.rays.n_rays, wl.rays.n_frames
-    want = pxm.WANT_GRID | pxm.WANT_POSE
+    tracking = wl.meta.get("mode") == "tracking"
+    want = pxm.WANT_POSE if tracking else pxm.WANT_GRID | pxm.WANT_POSE
     tv = wl.meta.get("tv", (1e-5, 1e-6, 1e-9))
-    if args.compare_per_frame:
-        print(json.dumps(compare_per_frame(wl, g, r, trgb, tdep, fw, args.steps, args.warmup)),
-              flush=True)
-        return
     tuned_ms = None
     if args.block or args.variant >= 0:
         pxm.set_tuning(args.block or 256, max(args.variant, 0))
@@ -236,9 +309,19 @@ def main():
         cache = os.path.join(ROOT, "gpurun_out", "tune.json") if os.path.isdir(
             os.path.join(ROOT, "gpurun_out")) else None
         (b_, v_), tuned_ms = Autotuner(cache, reps=3, warmup=1).tune(
-            g, r, wl.opts, trgb, tdep, fw, pxm.WANT_GRID | pxm.WANT_POSE, force=True)
+            g, r, wl.opts, trgb, tdep, fw, want, force=True)
         log("autotuned launch shape: %d rays/workgroup, variant %d (%s)" % (
             b_, v_, ", ".join("%s: %.2f ms" % kv for kv in sorted(tuned_ms.items()))))
+    if args.compare_per_frame:
+        out = compare_per_frame(wl, g, r, trgb, tdep, fw, args.steps, args.warmup)
+        out["config"]["block"], out["config"]["variant"] = pxm.get_tuning()
+        print(json.dumps(out), flush=True)
+        return
+    if tracking:
+        out = tracking_bench(wl, g, r, trgb, tdep, fw, args)
+        out["autotune_ms"] = tuned_ms
+        print(json.dumps(out), flush=True)
+        return
     block, variant = pxm.get_tuning()
 
     rgb = torch.empty(n, 3, device=dev)

@@ -183,7 +183,10 @@ int pxm_tv_grad(const pxm_grid *grid, float lambda_density, float lambda_sh, flo
  *   stats        [4] int64                   (accumulated with PXM_WANT_STATS:
  *                 occupied samples, allocated corners of those, allocated
  *                 corners that received a gradient, rays with a valid target)
- * ws / ws_bytes: workspace of at least pxm_workspace_bytes(..., want) bytes.
+ * ws / ws_bytes: device workspace of at least pxm_workspace_bytes(..., want)
+ *   bytes holding the tile-queue counters of the persistent launch form.  It
+ *   must be zeroed before its first use; every call leaves it zeroed again.
+ *   Calls that share one workspace must not run concurrently.
  */
 int pxm_render_fused(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
                      const float *tgt_rgb, const float *tgt_depth, const float *frame_weight,

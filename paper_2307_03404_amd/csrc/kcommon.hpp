@@ -299,6 +299,16 @@ __device__ __forceinline__ bool sample_at(const KGrid& g, const Ray& ray, int64_
     return true;
 }
 
+// Workgroup b of G -> work item, grouping consecutive items on one XCD: the
+// hardware deals workgroups round-robin over the 8 XCDs, each with its own
+// L2, and neighbouring items (ray tiles, grid bricks) read the same vertices.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+    const int64_t q = G / 8, rem = G % 8;
+    const int64_t x = b % 8, j = b / 8;
+    const int64_t start = x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;
+    return start + j;
+}
+
 // ---------------------------------------------------------------------------
 // empty-space skipping with the occupancy bitfield
 // ---------------------------------------------------------------------------

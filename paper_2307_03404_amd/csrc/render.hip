@@ -399,16 +399,6 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
     }
 }
 
-// Workgroup -> ray tile, grouping consecutive tiles on one XCD: the hardware
-// deals workgroups round-robin over the 8 XCDs, each with its own L2, and
-// neighbouring tiles gather the same vertices.
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
-    const int64_t q = G / 8, rem = G % 8;
-    const int64_t x = b % 8, j = b / 8;
-    const int64_t start = x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;
-    return start + j;
-}
-
 template <bool GRID, bool POSE, bool VIEW>
 __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
                                                const float* __restrict__ tgt_rgb,
@@ -430,6 +420,9 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
         __syncthreads();
     }
     const int64_t n_tiles = (rs.n + blockDim.x - 1) / blockDim.x;
+    // Persistent form: workgroups take tiles in order from one queue counter
+    // (ws[0]), so the tiles in flight at any time are neighbours in the
+    // image and gather from one compact region of the grid.
     for (;;) {
         int64_t tile;
         if (persistent) {
@@ -575,12 +568,32 @@ static int device_cus() {
     return cus;
 }
 
+// Persistent grid: as many workgroups as the device holds at once (from the
+// kernel's register and LDS use), never more than there are tiles.
 template <bool GRID, bool POSE, bool VIEW>
-static void fused_go(dim3 grid, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
+static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
+    static int per_cu[4] = {0, 0, 0, 0};                  // by block 64/128/256/512
+    const int slot = block == 64 ? 0 : block == 128 ? 1 : block == 256 ? 2 : 3;
+    if (per_cu[slot] <= 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW>, block, lds)
+                != hipSuccess || n <= 0)
+            n = 1;
+        per_cu[slot] = n;
+    }
+    static int cus = device_cus();
+    const int64_t cap = (int64_t)cus * per_cu[slot];
+    return (unsigned)(tiles < cap ? tiles : cap);
+}
+
+template <bool GRID, bool POSE, bool VIEW>
+static void fused_go(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
                      const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                      const float* fw, float* rgb, float* depth, double* loss, float* grad,
                      double* gp, int64_t* stats, unsigned* ws, int persistent) {
     const size_t lds = GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float) : 0;
+    const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW>(block.x, lds, tiles)
+                               : (unsigned)tiles);
     hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW>), grid, block, lds, st, g, rs, op, tgt_rgb,
                        tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent);
 }
@@ -597,13 +610,9 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
             block /= 2;
     }
     const int64_t tiles = (rs.n + block - 1) / block;
-    unsigned nblk = (unsigned)tiles;
-    if (variant == 1) {
-        static int cus = device_cus();
-        const int64_t cap = (int64_t)cus * (2048 / block);   // 8 waves per SIMD-set worth
-        nblk = (unsigned)(tiles < cap ? tiles : cap);
-    }
-    const dim3 grid(nblk), blk(block);
+    if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;  // 32-bit grid and queue counters
+    const dim3 blk(block);
+    const int64_t grid = tiles;
     const bool G = want & 1, P = want & 2, V = (op.flags & 1) != 0;
     int64_t* sp = (want & 4) ? stats : nullptr;
     if (G && P) {

@@ -81,6 +81,13 @@ __device__ __forceinline__ int stage_at(int i, int ray_lane) {
 // the scatter
 // ---------------------------------------------------------------------------
 
+// A pass whose groups cover at most this many lanes is summed lane by lane
+// (scalar broadcast of each member's weights) instead of on the matrix cores,
+// and written out without the cache: rays of a sparse pixel subset rarely
+// share a cell, and one MFMA pass plus its cache update costs as much as
+// about this many broadcast members.
+constexpr int SMALL_PASS_LANES = 16;
+
 // Gradient of one sample: dL/d sigma_raw (gsig) and dL/ds_c (gs[c]) to be
 // spread over the corners of cell `cell` (link base `key`, corner ids idx[],
 // trilinear weights w[]).  Must be reached by every lane of the wave.
@@ -106,10 +113,14 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
 #pragma unroll
         for (int m = 0; m < REC; ++m) wc.sb[stage_at(m, lane)] = G[m];
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     while (pending) {
         // discover up to four groups (distinct cells) for this pass
         int grp = -1, ng = 0;
         int leader[4] = {0, 0, 0, 0};
+        unsigned long long members[4] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             if (pending) {
@@ -119,25 +130,60 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
                 const int64_t k0 = (int64_t)(((uint64_t)(uint32_t)khi << 32) | (uint32_t)klo);
                 const bool mine = have && key == k0 && grp < 0;
                 if (mine) grp = g;
-                pending &= ~__ballot(mine);
+                members[g] = __ballot(mine);
+                pending &= ~members[g];
                 leader[g] = ld;
                 ng = g + 1;
             }
         }
-        // W rows of this pass
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-#pragma unroll
-            for (int b = 0; b < 8; ++b) wc.sa[stage_at(g * 8 + b, lane)] = (grp == g) ? w[b] : 0.f;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // C = W^T G over the 64 lanes, two lanes per instruction
         f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        const float* pa = wc.sa + ((h << 5) + j) * STAGE_LD;
-        const float* pb = wc.sb + ((h << 5) + j) * STAGE_LD;
+        const int covered = __popcll(members[0] | members[1] | members[2] | members[3]);
+        if (covered > SMALL_PASS_LANES) {
+            // W rows of this pass
 #pragma unroll
-        for (int c = 0; c < 32; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[c], pb[c], acc, 0, 0, 0);
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) wc.sa[stage_at(g * 8 + b, lane)] = (grp == g) ? w[b] : 0.f;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // C = W^T G over the 64 lanes, two lanes per instruction
+            const float* pa = wc.sa + ((h << 5) + j) * STAGE_LD;
+            const float* pb = wc.sb + ((h << 5) + j) * STAGE_LD;
+#pragma unroll
+            for (int c = 0; c < 32; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[c], pb[c], acc, 0, 0, 0);
+        } else {
+            // the same totals in the same register layout, member by member:
+            // lane (h, j) adds w_{4h+r}(s) * G[s][j] into row 4h + r of group g;
+            // then straight to HBM (each atomic instruction covers the two
+            // 112-byte records of corners r and 4 + r), bypassing the cache
+            // that small groups would mostly evict from
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (g >= ng) continue;                      // wave-uniform
+                unsigned long long mb = members[g];
+                while (mb) {
+                    const int src = __ffsll((long long)mb) - 1;
+                    mb &= mb - 1;
+                    const float gv = wc.sb[stage_at(j, src)];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float w0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w[r]), src));
+                        const float w1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w[4 + r]), src));
+                        acc[4 * g + r] = fmaf(h ? w1 : w0, gv, acc[4 * g + r]);
+                    }
+                }
+                const int ld = leader[g];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int id0 = __builtin_amdgcn_readlane(idx[r], ld);
+                    const int id1 = __builtin_amdgcn_readlane(idx[4 + r], ld);
+                    const int vid = h ? id1 : id0;
+                    if (vid >= 0 && j < REC) unsafeAtomicAdd(grad + (int64_t)vid * REC + j, acc[4 * g + r]);
+                }
+            }
+            continue;
+        }
         // accumulator r holds row 8*(r/4) + 4*h + r%4 = group r/4, corner 4*h + r%4, column j
 #pragma unroll
         for (int r = 0; r < 16; ++r) {

@@ -11,7 +11,11 @@
 // One workgroup per brick of 8^3 lattice vertices.  It stages the brick and a
 // one-vertex halo (10^3 positions) in LDS four fields at a time, so each
 // allocated record is fetched about twice instead of once per neighbour that
-// reads it; bricks without an allocated vertex leave after their link loads.
+// reads it.  Bricks are dealt to XCDs in contiguous runs so that the halo a
+// brick shares with its neighbours is read through the same L2.  A brick is
+// left at once when the occupancy bitfield says its cells have no allocated
+// corner, else after its link loads if none of its vertices is allocated; the
+// arithmetic runs over a compacted list of the allocated vertices only.
 #include "internal.hpp"
 
 namespace pxm {
@@ -28,17 +32,22 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
                                                    int nbz) {
     __shared__ int s_id[TH3];
     __shared__ float s_v[4][TH3];          // four field planes of the current chunk
-    __shared__ int s_any;
+    __shared__ int s_list[TB * TB * TB];   // halo positions of allocated brick vertices
+    __shared__ int s_n;
     const int t = threadIdx.x;
-    const int64_t brick = blockIdx.x;
+    const int64_t brick = xcd_tile(blockIdx.x, gridDim.x);
     const int bz = (int)(brick % nbz), by = (int)((brick / nbz) % nby);
     const int bx = (int)(brick / ((int64_t)nbz * nby));
     const int x0 = bx * TB, y0 = by * TB, z0 = bz * TB;
     const int X = g.R[0], Y = g.R[1], Z = g.R[2];
-    if (t == 0) s_any = 0;
-    __syncthreads();
+    // An allocated vertex v of this brick is a corner of cell min(v, R-2) per
+    // axis, which lies in cell brick (bx, by, bz) whenever that brick exists.
+    if (g.occ1 && bx < g.B[0] && by < g.B[1] && bz < g.B[2]) {
+        const int c[3] = {x0, y0, z0};
+        if (brick_empty(g, c)) return;                      // workgroup-uniform
+    }
+    if (t == 0) s_n = 0;
     // link ids of the halo box (-1 outside the lattice or empty)
-    bool any = false;
     for (int p = t; p < TH3; p += TV_THREADS) {
         const int hx = p / (TH * TH), hy = (p / TH) % TH, hz = p % TH;
         const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
@@ -48,11 +57,22 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             id = ((uint32_t)id < (uint64_t)g.n_alloc) ? id : -1;
         }
         s_id[p] = id;
-        if (id >= 0 && hx >= 1 && hx <= TB && hy >= 1 && hy <= TB && hz >= 1 && hz <= TB) any = true;
     }
-    if (any) s_any = 1;
     __syncthreads();
-    if (!s_any) return;                                     // workgroup-uniform
+    // compact the allocated vertices of the brick (the order is irrelevant:
+    // every vertex is computed and written by one thread)
+    for (int v = t; v < TB * TB * TB; v += TV_THREADS) {
+        const int c = hidx(v / (TB * TB) + 1, (v / TB) % TB + 1, v % TB + 1);
+        const bool a = s_id[c] >= 0;                        // outside the lattice reads -1
+        const unsigned long long m = __ballot(a);
+        int base = 0;
+        if (lane_id() == 0 && m) base = atomicAdd(&s_n, __popcll(m));
+        base = __shfl(base, 0);
+        if (a) s_list[base + __popcll(m & ((1ull << lane_id()) - 1))] = c;
+    }
+    __syncthreads();
+    const int n = s_n;
+    if (n == 0) return;                                     // workgroup-uniform
 #pragma unroll 1
     for (int q = 0; q < 7; ++q) {
         for (int p = t; p < TH3; p += TV_THREADS) {
@@ -65,15 +85,12 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             s_v[3][p] = w.w;
         }
         __syncthreads();
-        // 512 interior vertices x 4 fields, 8 items per thread
-        for (int it = t; it < TB * TB * TB * 4; it += TV_THREADS) {
-            const int f = it & 3, v = it >> 2;
-            const int ix = v / (TB * TB) + 1, iy = (v / TB) % TB + 1, iz = v % TB + 1;
+        for (int it = t; it < 4 * n; it += TV_THREADS) {
+            const int f = it & 3;
+            const int c = s_list[it >> 2];
+            const int ix = c / (TH * TH), iy = (c / TH) % TH, iz = c % TH;
             const int x = x0 + ix - 1, y = y0 + iy - 1, z = z0 + iz - 1;
-            if (x >= X || y >= Y || z >= Z) continue;
-            const int c = hidx(ix, iy, iz);
             const int id = s_id[c];
-            if (id < 0) continue;
             const float* plane = s_v[f];
             auto val = [&](int p) -> float { return plane[p]; };
             const int m = 4 * q + f;
@@ -81,29 +98,29 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             const float v0 = val(c);
             float acc = 0.f;
             if (x < X - 1 && y < Y - 1 && z < Z - 1) {
-                const float dx = val(hidx(ix + 1, iy, iz)) - v0;
-                const float dy = val(hidx(ix, iy + 1, iz)) - v0;
-                const float dz = val(hidx(ix, iy, iz + 1)) - v0;
+                const float dx = val(c + TH * TH) - v0;
+                const float dy = val(c + TH) - v0;
+                const float dz = val(c + 1) - v0;
                 acc -= (dx + dy + dz) * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            if (x >= 1 && y < Y - 1 && z < Z - 1 && s_id[hidx(ix - 1, iy, iz)] >= 0) {
-                const float a0 = val(hidx(ix - 1, iy, iz));
+            if (x >= 1 && y < Y - 1 && z < Z - 1 && s_id[c - TH * TH] >= 0) {
+                const float a0 = val(c - TH * TH);
                 const float dx = v0 - a0;
-                const float dy = val(hidx(ix - 1, iy + 1, iz)) - a0;
-                const float dz = val(hidx(ix - 1, iy, iz + 1)) - a0;
+                const float dy = val(c - TH * TH + TH) - a0;
+                const float dz = val(c - TH * TH + 1) - a0;
                 acc += dx * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            if (y >= 1 && x < X - 1 && z < Z - 1 && s_id[hidx(ix, iy - 1, iz)] >= 0) {
-                const float b0 = val(hidx(ix, iy - 1, iz));
-                const float dx = val(hidx(ix + 1, iy - 1, iz)) - b0;
+            if (y >= 1 && x < X - 1 && z < Z - 1 && s_id[c - TH] >= 0) {
+                const float b0 = val(c - TH);
+                const float dx = val(c - TH + TH * TH) - b0;
                 const float dy = v0 - b0;
-                const float dz = val(hidx(ix, iy - 1, iz + 1)) - b0;
+                const float dz = val(c - TH + 1) - b0;
                 acc += dy * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            if (z >= 1 && x < X - 1 && y < Y - 1 && s_id[hidx(ix, iy, iz - 1)] >= 0) {
-                const float c0 = val(hidx(ix, iy, iz - 1));
-                const float dx = val(hidx(ix + 1, iy, iz - 1)) - c0;
-                const float dy = val(hidx(ix, iy + 1, iz - 1)) - c0;
+            if (z >= 1 && x < X - 1 && y < Y - 1 && s_id[c - 1] >= 0) {
+                const float c0 = val(c - 1);
+                const float dx = val(c - 1 + TH * TH) - c0;
+                const float dy = val(c - 1 + TH) - c0;
                 const float dz = v0 - c0;
                 acc += dz * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }

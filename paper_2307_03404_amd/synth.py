@@ -489,7 +489,7 @@ def config3(grid_scene=None) -> Workload:
     tg = Targets(rgb, depth, frame_weights(depth, rays.frame_offsets, True))
     opts = Opts(step_vox=0.5, max_samples=128, depth_loss=DEPTH_L1)
     return Workload("c3_track32_16frames", grid, rays, tg, opts,
-                    true_c2w=np.asarray(true, np.float32), meta={"scene": scene})
+                    true_c2w=np.asarray(true, np.float32), meta={"scene": scene, "mode": "tracking", "iters": 20})
 
 
 _C4_CACHE = {}
