@@ -164,7 +164,8 @@ int pxm_render_backward_pose(const pxm_grid *grid, const pxm_rays *rays, const p
  * allocated and not on an upper face, lambda_0 = lambda_density for the
  * density field and lambda_sh for each of the 27 SH fields.  dTV/d record is
  * added into grad_data [n_alloc][28] (accumulated, gather form: one writer
- * per vertex, no atomics).
+ * per vertex, no atomics).  With grid->occ set, 8^3 bricks whose cells have
+ * no allocated corner are skipped.
  */
 int pxm_tv_grad(const pxm_grid *grid, float lambda_density, float lambda_sh, float eps,
                 float *grad_data, void *stream);

@@ -29,13 +29,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int CACHE_SLOTS = 64;
 constexpr int STAGE_LD = 33;                              // padded row: conflict-free reads
 constexpr int STAGE_FLOATS = 64 * STAGE_LD;               // one operand: 64 rows (h*32 + i)
-constexpr int WAVE_LDS_FLOATS = CACHE_SLOTS * (REC + 1) + 2 * STAGE_FLOATS;
+constexpr int WAVE_LDS_FLOATS = CACHE_SLOTS * (REC + 1) + 2 * STAGE_FLOATS + WAVE * 8;
 
 struct WaveCache {
     int* key;       // [CACHE_SLOTS], -1 = free
     float* data;    // [CACHE_SLOTS][REC]
     float* sa;      // staged W operand
     float* sb;      // staged G operand
+    float* sw;      // [WAVE][8] each lane's trilinear weights (16-byte aligned)
 };
 
 __device__ __forceinline__ WaveCache wave_cache(float* smem) {
@@ -43,7 +44,7 @@ __device__ __forceinline__ WaveCache wave_cache(float* smem) {
     float* base = smem + (size_t)w * WAVE_LDS_FLOATS;
     float* data = base + CACHE_SLOTS;
     float* sa = data + CACHE_SLOTS * REC;
-    return WaveCache{reinterpret_cast<int*>(base), data, sa, sa + STAGE_FLOATS};
+    return WaveCache{reinterpret_cast<int*>(base), data, sa, sa + STAGE_FLOATS, sa + 2 * STAGE_FLOATS};
 }
 
 // Mark every slot free; the caller synchronises the workgroup afterwards.
@@ -112,6 +113,9 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
         }
 #pragma unroll
         for (int m = 0; m < REC; ++m) wc.sb[stage_at(m, lane)] = G[m];
+        float4* sw = reinterpret_cast<float4*>(wc.sw + lane * 8);
+        sw[0] = make_float4(w[0], w[1], w[2], w[3]);
+        sw[1] = make_float4(w[4], w[5], w[6], w[7]);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -166,12 +170,11 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
                     const int src = __ffsll((long long)mb) - 1;
                     mb &= mb - 1;
                     const float gv = wc.sb[stage_at(j, src)];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float w0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w[r]), src));
-                        const float w1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w[4 + r]), src));
-                        acc[4 * g + r] = fmaf(h ? w1 : w0, gv, acc[4 * g + r]);
-                    }
+                    const float4 wv = *reinterpret_cast<const float4*>(wc.sw + src * 8 + 4 * h);
+                    acc[4 * g + 0] = fmaf(wv.x, gv, acc[4 * g + 0]);
+                    acc[4 * g + 1] = fmaf(wv.y, gv, acc[4 * g + 1]);
+                    acc[4 * g + 2] = fmaf(wv.z, gv, acc[4 * g + 2]);
+                    acc[4 * g + 3] = fmaf(wv.w, gv, acc[4 * g + 3]);
                 }
                 const int ld = leader[g];
 #pragma unroll
