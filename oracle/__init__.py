@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark may import this package; the product path never does.
 It shares no code with the HIP kernels.  Its C core (``oracle.c``) follows the
 paper's equations one ray at a time in double precision; this module only
-marshals numpy arrays, plus two small textbook pieces in numpy (the SE(3)
-exponential map and an Adam step) used by the tracking pins.
+marshals numpy arrays, plus small textbook pieces in numpy (the SE(3)
+exponential map, an Adam step for tracking and a sparse RMSProp step for
+mapping).
 
 Parity unpinned by the paper: the colour activation, the SH sign/order
 convention, the se(3) pose parametrisation, the default (position-only)
@@ -268,3 +269,24 @@ def adam_pose_step(c2w, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     upd = -lr * mh / (np.sqrt(vh) + eps)
     out = np.stack([apply_left(upd[f], c2w[f]) for f in range(len(c2w))])
     return out, m, v
+
+
+def rmsprop_grid(data, grad, state, lr_density, lr_sh, alpha, eps):
+    """One sparse RMSProp step on the vertex records (mapping optimiser,
+    Sec. 5.4).  A record is touched when any of its 28 gradient entries is
+    non-zero; touched records update every entry,
+        v <- alpha v + (1 - alpha) g^2,   x <- x - lr g / (sqrt(v) + eps),
+    with lr_density for entry 0 and lr_sh for the 27 SH entries; untouched
+    records keep both their values and their running average.  Returns the
+    new (data, state) in FP64; the gradient is consumed (the caller zeroes it)."""
+    data = np.array(data, np.float64)
+    state = np.array(state, np.float64)
+    g = np.asarray(grad, np.float64)
+    touched = np.any(g != 0.0, axis=1)
+    lr = np.full(NREC, float(lr_sh))
+    lr[0] = float(lr_density)
+    gt = g[touched]
+    v = alpha * state[touched] + (1.0 - alpha) * gt * gt
+    state[touched] = v
+    data[touched] = data[touched] - lr[None, :] * gt / (np.sqrt(v) + eps)
+    return data, state

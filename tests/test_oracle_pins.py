@@ -504,3 +504,49 @@ def test_adam_step_matches_torch():
         expect = np.stack([oracle.apply_left(step_torch[f], c2w[f]) for f in range(F)])
         np.testing.assert_allclose(new, expect, atol=1e-14)
         c2w = new
+
+
+def test_rmsprop_dense_matches_torch():
+    """Every record touched: the sparse step is plain RMSProp (torch's
+    non-centred form, two parameter groups for the density and SH learning
+    rates), over several steps."""
+    import torch
+    rng = np.random.default_rng(52)
+    n = 5
+    x0 = rng.normal(size=(n, oracle.NREC))
+    dens = torch.tensor(x0[:, :1].copy(), requires_grad=True)
+    sh = torch.tensor(x0[:, 1:].copy(), requires_grad=True)
+    opt = torch.optim.RMSprop([{"params": [dens], "lr": 0.3}, {"params": [sh], "lr": 0.02}],
+                              alpha=0.95, eps=1e-8)
+    data, state = x0.copy(), np.zeros_like(x0)
+    for _ in range(4):
+        g = rng.normal(size=(n, oracle.NREC))
+        opt.zero_grad()
+        dens.grad = torch.from_numpy(g[:, :1].copy())
+        sh.grad = torch.from_numpy(g[:, 1:].copy())
+        opt.step()
+        data, state = oracle.rmsprop_grid(data, g, state, 0.3, 0.02, 0.95, 1e-8)
+        ref = np.concatenate([dens.detach().numpy(), sh.detach().numpy()], axis=1)
+        np.testing.assert_allclose(data, ref, rtol=0, atol=1e-13)
+
+
+def test_rmsprop_sparse_rule():
+    """Untouched records keep value and running average (dense RMSProp would
+    decay the average); a record with one non-zero entry is touched as a
+    whole: its other entries keep their values but their averages decay."""
+    rng = np.random.default_rng(53)
+    n = 4
+    data = rng.normal(size=(n, oracle.NREC))
+    state = rng.uniform(0.1, 1.0, size=(n, oracle.NREC))
+    g = np.zeros((n, oracle.NREC))
+    g[1] = rng.normal(size=oracle.NREC)
+    g[3, 7] = 0.5
+    new, st = oracle.rmsprop_grid(data, g, state, 0.1, 0.01, 0.9, 1e-8)
+    for r in (0, 2):
+        assert np.array_equal(new[r], data[r]) and np.array_equal(st[r], state[r])
+    others = np.arange(oracle.NREC) != 7
+    assert np.array_equal(new[3, others], data[3, others])
+    np.testing.assert_allclose(st[3, others], 0.9 * state[3, others], rtol=1e-15)
+    v = 0.9 * state[3, 7] + 0.1 * 0.25
+    np.testing.assert_allclose(new[3, 7], data[3, 7] - 0.01 * 0.5 / (np.sqrt(v) + 1e-8), rtol=1e-14)
+    np.testing.assert_allclose(st[1], 0.9 * state[1] + 0.1 * g[1] ** 2, rtol=1e-15)
