@@ -207,6 +207,22 @@ int pxm_pose_adam(int32_t n_frames, float *c2w, double *grad_pose, double *state
                   float beta1, float beta2, float eps, void *stream);
 
 /*
+ * Mapping update (Sec. 5.4: RMSProp for mapping): one sparse RMSProp step
+ * over the vertex records.  A record is touched when any of its 28 entries
+ * of grad_data is non-zero; for touched records, entry by entry,
+ *   state <- alpha state + (1 - alpha) g^2,
+ *   data  <- data - lr g / (sqrt(state) + eps),
+ * with lr = lr_density for entry 0 and lr_sh for the 27 SH entries.
+ * Untouched records keep their values and running averages (the rule of the
+ * Plenoxel optimiser the method builds on; the paper states none).
+ * grad_data is read and then zeroed, so one call ends a mapping iteration.
+ *   data, grad_data, state [n_alloc][28] f32, 16-byte aligned (in/out;
+ *   state starts zeroed).  n_alloc == 0 is a no-op.
+ */
+int pxm_grid_rmsprop(int64_t n_alloc, float *data, float *grad_data, float *state,
+                     float lr_density, float lr_sh, float alpha, float eps, void *stream);
+
+/*
  * Occupancy bitfield for empty-space skipping (an exact acceleration: a cell
  * whose 8 corners are all empty interpolates to zero density and carries no
  * light or gradient).  Level 0 holds one bit per cell ((x*(Ry-1)+y)*W0 + z/32,

@@ -9,6 +9,8 @@
 * TrackingGraph: `iters` tracking iterations (fused forward + loss + pose
   backward for every frame, then the Adam pose update) captured once into a
   HIP graph and replayed without host round trips (Sec. 5.3-5.4).
+* MappingLoop: mapping iterations over keyframes (random rays, fused grid
+  gradient, TV, sparse RMSProp), and image_metrics (PSNR, L1 depth).
 """
 from __future__ import annotations
 
@@ -209,3 +211,82 @@ class TrackingGraph:
         """Restore the starting poses and clear the optimiser state."""
         self.rays.c2w.copy_(c2w)
         self.state.zero_()
+
+
+class MappingLoop:
+    """Mapping iterations over a set of keyframes (Sec. 5.4, Sec. 6.1).
+
+    Each iteration draws `n_rays` rays uniformly (with replacement) from all
+    keyframe pixels, runs one fused launch for the loss and its grid gradient
+    (rays without a valid depth are dropped by the kernel; the loss weight is
+    1/M over the valid rays of the batch), adds the TV gradient and applies one
+    sparse RMSProp step to the vertex records, which also clears the gradient.
+    The random draw is the only host-side decision and stays on the device
+    (a seeded torch generator); `last_indices` keeps the rays of the latest
+    iteration so that a test can replay it.
+    """
+
+    def __init__(self, grid, keyframes, tgt_rgb, tgt_depth, opts, n_rays, lr_density, lr_sh,
+                 alpha=0.95, eps=1e-8, tv=(1e-5, 1e-6, 1e-9), seed=0):
+        dev = grid.data.device
+        self.grid, self.kf, self.opts = grid, keyframes, opts
+        self.tgt_rgb, self.tgt_depth = tgt_rgb, tgt_depth
+        self.n_rays = int(n_rays)
+        self.lr = (float(lr_density), float(lr_sh))
+        self.alpha, self.eps, self.tv = float(alpha), float(eps), tuple(tv)
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(int(seed))
+        self.grad = torch.zeros_like(grid.data)
+        self.state = torch.zeros_like(grid.data)
+        F = keyframes.c2w.shape[0]
+        self.loss = torch.zeros(F, dtype=torch.float64, device=dev)
+        self.ws = None
+        self.last_indices = None
+        self._frame_ids = torch.repeat_interleave(
+            torch.arange(F, device=dev),
+            (keyframes.frame_offsets[1:] - keyframes.frame_offsets[:-1]).long())
+
+    def sample(self, indices=None):
+        """The ray batch of one iteration: sorted keyframe ray indices -> CSR
+        rays (frames in order), their targets and the 1/M weight."""
+        kf, dev = self.kf, self.grid.data.device
+        n_all = int(kf.pix.shape[0])
+        if indices is None:
+            indices = torch.randint(0, n_all, (self.n_rays,), device=dev, generator=self.gen)
+        idx = torch.sort(indices).values
+        fid = self._frame_ids[idx]
+        F = kf.c2w.shape[0]
+        counts = torch.bincount(fid, minlength=F)
+        off = torch.zeros(F + 1, dtype=torch.int32, device=dev)
+        off[1:] = torch.cumsum(counts, 0).to(torch.int32)
+        rays = pxm.DeviceRays(kf.c2w, kf.intr, off, kf.pix[idx].contiguous())
+        rgb = self.tgt_rgb[idx].contiguous()
+        depth = self.tgt_depth[idx].contiguous()
+        valid = torch.isfinite(depth) & (depth > 0)
+        w = (1.0 / valid.sum().clamp(min=1).to(torch.float32)).expand(F).contiguous()
+        return idx, rays, rgb, depth, w
+
+    def step(self, indices=None):
+        idx, rays, rgb, depth, w = self.sample(indices)
+        self.last_indices = idx
+        if self.ws is None:
+            self.ws = pxm.new_workspace(self.grid, rays, self.opts, pxm.WANT_GRID)
+        self.loss.zero_()
+        pxm.render_fused(self.grid, rays, self.opts, rgb, depth, w, pxm.WANT_GRID, loss=self.loss,
+                         grad_data=self.grad, ws=self.ws)
+        if self.tv[0] or self.tv[1]:
+            pxm.tv_grad(self.grid, self.tv[0], self.tv[1], self.tv[2], self.grad)
+        pxm.grid_rmsprop(self.grid.data, self.grad, self.state, self.lr[0], self.lr[1],
+                         self.alpha, self.eps)
+        return self.loss.sum()
+
+
+def image_metrics(grid, rays, opts, tgt_rgb, tgt_depth):
+    """PSNR of the rendered colour and mean absolute z-depth error over the
+    pixels with a valid depth (the map-quality metrics of Sec. 6.1)."""
+    rgb, depth, _ = pxm.render_forward(grid, rays, opts)
+    valid = torch.isfinite(tgt_depth) & (tgt_depth > 0)
+    mse = ((rgb - tgt_rgb) ** 2)[valid].mean()
+    psnr = -10.0 * torch.log10(mse)
+    l1 = (depth - tgt_depth)[valid].abs().mean()
+    return float(psnr), float(l1)

@@ -275,4 +275,19 @@ int pxm_pose_adam(int32_t n_frames, float* c2w, double* grad_pose, double* state
                                      (hipStream_t)stream), "pose_adam");
 }
 
+int pxm_grid_rmsprop(int64_t n_alloc, float* data, float* grad_data, float* state, float lr_density,
+                     float lr_sh, float alpha, float eps, void* stream) {
+    if (n_alloc < 0 || n_alloc > INT32_MAX) return fail(PXM_INVALID_ARGUMENT, "n_alloc outside [0, 2^31)");
+    if (!finite(lr_density) || !finite(lr_sh) || !(lr_density >= 0.f) || !(lr_sh >= 0.f))
+        return fail(PXM_INVALID_ARGUMENT, "learning rates must be finite and >= 0");
+    if (!(alpha >= 0.f && alpha < 1.f)) return fail(PXM_INVALID_ARGUMENT, "alpha outside [0, 1)");
+    if (!(eps > 0.f) || !finite(eps)) return fail(PXM_INVALID_ARGUMENT, "eps must be finite and > 0");
+    if (n_alloc == 0) return PXM_OK;
+    if (!data || !grad_data || !state) return fail(PXM_INVALID_ARGUMENT, "a required array is NULL");
+    if (((uintptr_t)data | (uintptr_t)grad_data | (uintptr_t)state) & 15u)
+        return fail(PXM_INVALID_ARGUMENT, "data, grad_data and state must be 16-byte aligned");
+    return launched(pxm::launch_rmsprop(n_alloc, data, grad_data, state, lr_density, lr_sh, alpha,
+                                        eps, (hipStream_t)stream), "grid_rmsprop");
+}
+
 }  // extern "C"

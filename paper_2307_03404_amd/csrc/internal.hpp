@@ -36,4 +36,7 @@ hipError_t launch_occupancy(const KGrid& g, uint32_t* occ, hipStream_t st);
 hipError_t launch_adam(int F, float* c2w, double* grad_pose, double* state, float lr, float b1,
                        float b2, float eps, hipStream_t st);
 
+hipError_t launch_rmsprop(int64_t n, float* data, float* grad, float* avg, float lr_d, float lr_sh,
+                          float alpha, float eps, hipStream_t st);
+
 }  // namespace pxm

@@ -54,7 +54,8 @@ class _Opts(C.Structure):
 _lib = None
 _lock = threading.Lock()
 EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
-           "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_workspace_bytes",
+           "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_grid_rmsprop",
+           "pxm_workspace_bytes",
            "pxm_occupancy_words", "pxm_build_occupancy",
            "pxm_set_tuning", "pxm_get_tuning", "pxm_status_string", "pxm_last_error",
            "pxm_abi_version")
@@ -80,6 +81,7 @@ def lib():
         L.pxm_tv_grad.argtypes = [G, f32, f32, f32, P, P]
         L.pxm_render_fused.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P, sz, P]
         L.pxm_pose_adam.argtypes = [i32, P, P, P, f32, f32, f32, f32, P]
+        L.pxm_grid_rmsprop.argtypes = [i64, P, P, P, f32, f32, f32, f32, P]
         L.pxm_occupancy_words.argtypes = [G]
         L.pxm_occupancy_words.restype = sz
         L.pxm_build_occupancy.argtypes = [G, P, sz, P]
@@ -349,6 +351,17 @@ def pose_adam(c2w, grad_pose, state, lr, beta1=0.9, beta2=0.999, eps=1e-8, strea
     _check("pose_adam", lib().pxm_pose_adam(F, _ptr(c2w), _ptr(grad_pose), _ptr(state), float(lr),
                                             float(beta1), float(beta2), float(eps),
                                             _stream(stream)))
+
+
+def grid_rmsprop(data, grad_data, state, lr_density, lr_sh, alpha=0.95, eps=1e-8, stream=None):
+    """Sparse RMSProp step on the vertex records (in place); zeroes grad_data."""
+    n = int(data.shape[0])
+    _need(data, "data", torch.float32, (n, REC))
+    _need(grad_data, "grad_data", torch.float32, (n, REC))
+    _need(state, "state", torch.float32, (n, REC))
+    _check("grid_rmsprop", lib().pxm_grid_rmsprop(n, _ptr(data), _ptr(grad_data), _ptr(state),
+                                                  float(lr_density), float(lr_sh), float(alpha),
+                                                  float(eps), _stream(stream)))
 
 
 def set_tuning(block: int, variant: int):

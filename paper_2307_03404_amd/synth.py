@@ -137,6 +137,15 @@ def _rotation_about(axis, angle) -> np.ndarray:
     return np.eye(3) + np.sin(angle) * k + (1 - np.cos(angle)) * (k @ k)
 
 
+def perturb_grid(grid, rng, sigma_scale=(0.5, 1.5), sh_noise=0.05):
+    """A starting map for mapping: density scaled by U(sigma_scale), SH plus
+    N(0, sh_noise); same link table."""
+    data = grid.data.copy()
+    data[:, 0] *= rng.uniform(*sigma_scale, size=data.shape[0]).astype(np.float32)
+    data[:, 1:] += rng.normal(0.0, sh_noise, size=data[:, 1:].shape).astype(np.float32)
+    return dataclasses.replace(grid, data=data)
+
+
 def perturb_pose(c2w, rng, trans_sigma, rot_sigma_rad) -> np.ndarray:
     """Left-multiplied random rigid perturbation of a 3x4 pose."""
     axis = rng.normal(size=3)

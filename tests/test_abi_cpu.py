@@ -147,6 +147,14 @@ def test_tv_adam_and_tuning_checks():
     assert L.pxm_pose_adam(0, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.999, 1e-8, None) == 1
     assert L.pxm_pose_adam(2, FAKE, FAKE, FAKE, 1e-3, 1.0, 0.999, 1e-8, None) == 1
     assert L.pxm_pose_adam(2, FAKE, FAKE, None, 1e-3, 0.9, 0.999, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(0, None, None, None, 0.1, 0.01, 0.9, 1e-8, None) == 0
+    assert L.pxm_grid_rmsprop(-1, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, FAKE, FAKE, FAKE, 0.1, 0.01, 1.0, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, FAKE, FAKE, FAKE, -0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 0.0, None) == 1
+    assert L.pxm_grid_rmsprop(4, FAKE, None, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, FAKE + 4, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8,
+                              None) == 1
     assert L.pxm_set_tuning(100, 0) == 1
     assert L.pxm_set_tuning(256, 2) == 1
     before = pxm.get_tuning()
