@@ -55,6 +55,9 @@ def _load():
     lib.orc_backward.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64, i32,
                                  i32, P, P, P, P]
     lib.orc_backward.restype = None
+    lib.orc_pose_jacobian.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64,
+                                      i32, i32, P]
+    lib.orc_pose_jacobian.restype = None
     lib.orc_loss.argtypes = [i32, P, P, P, P, P, P, i32, f64, P, P, P]
     lib.orc_loss.restype = None
     lib.orc_tv.argtypes = [P, P, P, f64, f64, f64, P]
@@ -158,6 +161,64 @@ def fused(grid, rays, targets, opts, want_grid=True, want_pose=True):
     gd, gp = backward(grid, rays, opts, g_rgb, g_depth, want_grid, want_pose)
     return dict(rgb=rgb, depth=depth, nsamp=nsamp, stats=stats, loss=L, g_rgb=g_rgb,
                 g_depth=g_depth, grad_data=gd, grad_pose=gp)
+
+
+def pose_jacobian(grid, rays, opts, flags=None):
+    """Per-ray Jacobian f64[n,4,6] of (R, G, B, z-depth) with respect to the
+    left se(3) perturbation (rho, phi) of the ray's camera (Eq. 12-14)."""
+    lib = _load()
+    R, lo, vs, link, data = _grid_args(grid)
+    c2w, intr, off, pix = _ray_args(rays)
+    J = np.zeros((rays.n_rays, 4, 6))
+    fl = opts.flags if flags is None else flags
+    lib.orc_pose_jacobian(_p(R), _p(lo), vs, _p(link), _p(data), rays.n_frames, _p(c2w), _p(intr),
+                          _p(off), _p(pix), rays.n_rays, opts.step_vox, opts.max_samples,
+                          opts.t_near, opts.t_stop, opts.color_act, int(fl), _p(J))
+    return J
+
+
+def gn_system(grid, rays, targets, opts, flags=None):
+    """Gauss-Newton normal equations of each frame's squared photometric +
+    depth error (Eq. 4, 5 and 11 with the squared depth norm), linearised in
+    the frame's se(3) perturbation:
+        E_f = w_f sum_r (|C-hat_r - C_r|^2 + lambda (z_r - D_r)^2),
+        H_f = w_f sum_r J_r^T W J_r,  g_f = w_f sum_r J_r^T W e_r,
+    W = diag(1, 1, 1, lambda), e_r the 4-residual, over the rays with a valid
+    depth target.  Returns H f64[F,6,6], g f64[F,6], E f64[F]."""
+    rgb, depth, _, _ = render(grid, rays, opts)
+    J = pose_jacobian(grid, rays, opts, flags)
+    tr = np.asarray(targets.rgb, np.float64)
+    td = np.asarray(targets.depth, np.float64)
+    with np.errstate(invalid="ignore"):
+        valid = np.isfinite(td) & (td > 0)
+    lam = float(np.float32(opts.lambda_depth))
+    W = np.array([1.0, 1.0, 1.0, lam])
+    F = rays.n_frames
+    off = np.asarray(rays.frame_offsets)
+    H = np.zeros((F, 6, 6))
+    g = np.zeros((F, 6))
+    E = np.zeros(F)
+    for f in range(F):
+        sl = slice(int(off[f]), int(off[f + 1]))
+        v = valid[sl]
+        wf = float(np.float32(targets.frame_weight[f]))
+        e = np.concatenate([rgb[sl][v] - tr[sl][v], (depth[sl][v] - td[sl][v])[:, None]], axis=1)
+        Jf = J[sl][v]
+        H[f] = wf * np.einsum("rki,k,rkj->ij", Jf, W, Jf)
+        g[f] = wf * np.einsum("rki,k,rk->i", Jf, W, e)
+        E[f] = wf * float(np.sum(W[None, :] * e * e))
+    return H, g, E
+
+
+def gn_pose_step(c2w, H, g, damping):
+    """One damped Gauss-Newton step per frame: xi = -(H + damping I)^-1 g,
+    then the left retraction c2w <- exp(xi^) c2w."""
+    c2w = np.asarray(c2w, np.float64)
+    out = np.empty_like(c2w)
+    for f in range(c2w.shape[0]):
+        xi = -np.linalg.solve(H[f] + damping * np.eye(6), g[f])
+        out[f] = apply_left(xi, c2w[f])
+    return out
 
 
 def tv(grid, lambda_sigma, lambda_sh, eps, want_grad=True):

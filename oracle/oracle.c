@@ -550,6 +550,102 @@ void orc_loss(int32_t F, const int32_t *off, const double *rgb, const double *de
     }
 }
 
+/* Backward of one ray (Eq. 6-14 and Appendix A) for upstream gradients gC
+ * (dL/dC-hat) and gDz (dL/d z-depth): scatters into grad_data when it is not
+ * NULL and writes the ray's (rho, phi) pose gradient into out6 when that is
+ * not NULL. */
+static void ray_backward(const ogrid *g, const oopts *op, int32_t flags, const double *c2w_f,
+                         const double *intr_f, int u, int v, const double gC[3], double gDz,
+                         otrace *tr, double *grad_data, double out6[6])
+{
+    const double delta = op->step_vox;
+    const int act = op->act;
+    double o[3], d[3], s;
+    ray_through_pixel(c2w_f, intr_f, u, v, o, d, &s);
+    march(g, op, o, d, tr);
+    /* the loss sees z-depth = D-hat / s, so dL/dD-hat = g_depth / s */
+    const double gD = gDz / s;
+    double Y[NSH], GY[NSH][3];
+    sh_basis(d, Y);
+    sh_basis_grad(d, GY);
+    double prefC[3] = {0.0, 0.0, 0.0}, prefD = 0.0;
+    double go[3] = {0, 0, 0}, gd[3] = {0, 0, 0}, gview[3] = {0, 0, 0};
+    for (int i = 0; i < tr->n; ++i) {
+        /* inclusive prefixes sum_{j<=i} c_j w_j and sum_{j<=i} t_j w_j */
+        for (int ch = 0; ch < 3; ++ch) prefC[ch] += tr->c[i][ch] * tr->w[i];
+        prefD += tr->t[i] * tr->w[i];
+        const double Tn = tr->T[i + 1];
+        /* Eq. 9 and Eq. 10 */
+        double dL_dsigma = 0.0;
+        for (int ch = 0; ch < 3; ++ch)
+            dL_dsigma += gC[ch] * delta * (tr->c[i][ch] * Tn - tr->rgb[ch] + prefC[ch]);
+        dL_dsigma += gD * delta * (tr->t[i] * Tn - tr->D + prefD);
+        const double dL_dsraw = tr->sigma_raw[i] > 0.0 ? dL_dsigma : 0.0;
+        /* Eq. 8 through the colour activation */
+        double dL_ds[3];
+        for (int ch = 0; ch < 3; ++ch)
+            dL_ds[ch] = gC[ch] * tr->w[i] * act_df(act, tr->s[i][ch]);
+        if (dL_dsraw == 0.0 && dL_ds[0] == 0.0 && dL_ds[1] == 0.0 && dL_ds[2] == 0.0)
+            continue;
+        ocorners cc;
+        gather_cell(g, tr->q[i], &cc);
+        if (grad_data) {
+            double gval[NREC];
+            gval[0] = dL_dsraw;
+            for (int ch = 0; ch < 3; ++ch)
+                for (int k = 0; k < NSH; ++k) gval[1 + ch * NSH + k] = dL_ds[ch] * Y[k];
+            for (int b = 0; b < 8; ++b) {
+                if (cc.idx[b] < 0) continue;
+                double *dst = grad_data + cc.idx[b] * NREC;
+                for (int m = 0; m < NREC; ++m) {
+                    double add = cc.w[b] * gval[m];
+#pragma omp atomic
+                    dst[m] += add;
+                }
+            }
+        }
+        if (out6) {
+            double G[NREC][3];
+            interp_grad(&cc, G);
+            double gp[3];
+            for (int a = 0; a < 3; ++a) {
+                double acc = dL_dsraw * G[0][a];
+                for (int ch = 0; ch < 3; ++ch) {
+                    double dsa = 0.0;
+                    for (int k = 0; k < NSH; ++k) dsa += Y[k] * G[1 + ch * NSH + k][a];
+                    acc += dL_ds[ch] * dsa;
+                }
+                gp[a] = acc / g->vs;      /* voxel units -> world units */
+            }
+            /* Eq. 14: dp/do = 1, dp/dd = t_i */
+            for (int a = 0; a < 3; ++a) { go[a] += gp[a]; gd[a] += tr->t[i] * gp[a]; }
+            if (flags & FLAG_POSE_VIEWDIR) {
+                double val[NREC];
+                interp(&cc, val);
+                for (int a = 0; a < 3; ++a) {
+                    double acc = 0.0;
+                    for (int ch = 0; ch < 3; ++ch)
+                        for (int k = 0; k < NSH; ++k)
+                            acc += dL_ds[ch] * GY[k][a] * val[1 + ch * NSH + k];
+                    gview[a] += acc;
+                }
+            }
+        }
+    }
+    if (out6) {
+        double gphi[3];
+        gphi[0] = o[1] * go[2] - o[2] * go[1] + d[1] * gd[2] - d[2] * gd[1];
+        gphi[1] = o[2] * go[0] - o[0] * go[2] + d[2] * gd[0] - d[0] * gd[2];
+        gphi[2] = o[0] * go[1] - o[1] * go[0] + d[0] * gd[1] - d[1] * gd[0];
+        if (flags & FLAG_POSE_VIEWDIR) {
+            gphi[0] += d[1] * gview[2] - d[2] * gview[1];
+            gphi[1] += d[2] * gview[0] - d[0] * gview[2];
+            gphi[2] += d[0] * gview[1] - d[1] * gview[0];
+        }
+        for (int a = 0; a < 3; ++a) { out6[a] = go[a]; out6[3 + a] = gphi[a]; }
+    }
+}
+
 /*
  * Backward pass.  With the upstream gradients dL/dC-hat (g_rgb, [n][3]) and
  * dL/d(z-depth) (g_depth, [n]):
@@ -568,7 +664,6 @@ void orc_backward(const int32_t *R, const float *lo, double vs, const int32_t *l
     ogrid g;
     load_grid(&g, R, lo, vs, link, data);
     oopts op = {step_vox, max_samples, t_near, t_stop, act};
-    const double delta = step_vox;
 #pragma omp parallel
     {
         otrace tr;
@@ -577,96 +672,52 @@ void orc_backward(const int32_t *R, const float *lo, double vs, const int32_t *l
         for (int64_t r = 0; r < n_rays; ++r) {
             const double *gC = g_rgb + 3 * r;
             if (gC[0] == 0.0 && gC[1] == 0.0 && gC[2] == 0.0 && g_depth[r] == 0.0) continue;
-            int f = frame_of(off, F, r);
-            double o[3], d[3], s;
-            ray_through_pixel(c2w + 12 * f, intr + 4 * f, pix[2 * r], pix[2 * r + 1], o, d, &s);
-            march(&g, &op, o, d, &tr);
-            /* the loss sees z-depth = D-hat / s, so dL/dD-hat = g_depth / s */
-            const double gD = g_depth[r] / s;
-            double Y[NSH], GY[NSH][3];
-            sh_basis(d, Y);
-            sh_basis_grad(d, GY);
-            double prefC[3] = {0.0, 0.0, 0.0}, prefD = 0.0;
-            double go[3] = {0, 0, 0}, gd[3] = {0, 0, 0}, gview[3] = {0, 0, 0};
-            for (int i = 0; i < tr.n; ++i) {
-                /* inclusive prefixes sum_{j<=i} c_j w_j and sum_{j<=i} t_j w_j */
-                for (int ch = 0; ch < 3; ++ch) prefC[ch] += tr.c[i][ch] * tr.w[i];
-                prefD += tr.t[i] * tr.w[i];
-                const double Tn = tr.T[i + 1];
-                /* Eq. 9 and Eq. 10 */
-                double dL_dsigma = 0.0;
-                for (int ch = 0; ch < 3; ++ch)
-                    dL_dsigma += gC[ch] * delta * (tr.c[i][ch] * Tn - tr.rgb[ch] + prefC[ch]);
-                dL_dsigma += gD * delta * (tr.t[i] * Tn - tr.D + prefD);
-                const double dL_dsraw = tr.sigma_raw[i] > 0.0 ? dL_dsigma : 0.0;
-                /* Eq. 8 through the colour activation */
-                double dL_ds[3];
-                for (int ch = 0; ch < 3; ++ch)
-                    dL_ds[ch] = gC[ch] * tr.w[i] * act_df(act, tr.s[i][ch]);
-                if (dL_dsraw == 0.0 && dL_ds[0] == 0.0 && dL_ds[1] == 0.0 && dL_ds[2] == 0.0)
-                    continue;
-                ocorners cc;
-                gather_cell(&g, tr.q[i], &cc);
-                if (grad_data) {
-                    double gval[NREC];
-                    gval[0] = dL_dsraw;
-                    for (int ch = 0; ch < 3; ++ch)
-                        for (int k = 0; k < NSH; ++k) gval[1 + ch * NSH + k] = dL_ds[ch] * Y[k];
-                    for (int b = 0; b < 8; ++b) {
-                        if (cc.idx[b] < 0) continue;
-                        double *dst = grad_data + cc.idx[b] * NREC;
-                        for (int m = 0; m < NREC; ++m) {
-                            double add = cc.w[b] * gval[m];
+            const int f = frame_of(off, F, r);
+            double six[6];
+            ray_backward(&g, &op, flags, c2w + 12 * f, intr + 4 * f, pix[2 * r], pix[2 * r + 1],
+                         gC, g_depth[r], &tr, grad_data, grad_pose ? six : NULL);
+            if (grad_pose) {
+                double *dst = grad_pose + 6 * f;
+                for (int a = 0; a < 6; ++a) {
 #pragma omp atomic
-                            dst[m] += add;
-                        }
-                    }
-                }
-                if (grad_pose) {
-                    double G[NREC][3];
-                    interp_grad(&cc, G);
-                    double gp[3];
-                    for (int a = 0; a < 3; ++a) {
-                        double acc = dL_dsraw * G[0][a];
-                        for (int ch = 0; ch < 3; ++ch) {
-                            double dsa = 0.0;
-                            for (int k = 0; k < NSH; ++k) dsa += Y[k] * G[1 + ch * NSH + k][a];
-                            acc += dL_ds[ch] * dsa;
-                        }
-                        gp[a] = acc / g.vs;       /* voxel units -> world units */
-                    }
-                    /* Eq. 14: dp/do = 1, dp/dd = t_i */
-                    for (int a = 0; a < 3; ++a) { go[a] += gp[a]; gd[a] += tr.t[i] * gp[a]; }
-                    if (flags & FLAG_POSE_VIEWDIR) {
-                        double val[NREC];
-                        interp(&cc, val);
-                        for (int a = 0; a < 3; ++a) {
-                            double acc = 0.0;
-                            for (int ch = 0; ch < 3; ++ch)
-                                for (int k = 0; k < NSH; ++k)
-                                    acc += dL_ds[ch] * GY[k][a] * val[1 + ch * NSH + k];
-                            gview[a] += acc;
-                        }
-                    }
+                    dst[a] += six[a];
                 }
             }
-            if (grad_pose) {
-                double gphi[3];
-                gphi[0] = o[1] * go[2] - o[2] * go[1] + d[1] * gd[2] - d[2] * gd[1];
-                gphi[1] = o[2] * go[0] - o[0] * go[2] + d[2] * gd[0] - d[0] * gd[2];
-                gphi[2] = o[0] * go[1] - o[1] * go[0] + d[0] * gd[1] - d[1] * gd[0];
-                if (flags & FLAG_POSE_VIEWDIR) {
-                    gphi[0] += d[1] * gview[2] - d[2] * gview[1];
-                    gphi[1] += d[2] * gview[0] - d[0] * gview[2];
-                    gphi[2] += d[0] * gview[1] - d[1] * gview[0];
-                }
-                double *dst = grad_pose + 6 * f;
-                for (int a = 0; a < 3; ++a) {
-#pragma omp atomic
-                    dst[a] += go[a];
-#pragma omp atomic
-                    dst[3 + a] += gphi[a];
-                }
+        }
+        trace_free(&tr);
+    }
+}
+
+/*
+ * Per-ray pose Jacobian of the rendered outputs (colour R, G, B and z-depth)
+ * with respect to the left se(3) perturbation (rho, phi): row k of J[r] is
+ * the pose gradient of output k alone (upstream 1 on output k, 0 elsewhere),
+ * so J is built from the same Eq. 12-14 chain as the pose gradient.
+ *   J: [n][4][6], fully written (rows of rays that miss the grid are 0).
+ */
+void orc_pose_jacobian(const int32_t *R, const float *lo, double vs, const int32_t *link,
+                       const float *data, int32_t F, const double *c2w, const double *intr,
+                       const int32_t *off, const int32_t *pix, int64_t n_rays,
+                       double step_vox, int32_t max_samples, double t_near, double t_stop,
+                       int32_t act, int32_t flags, double *J)
+{
+    ogrid g;
+    load_grid(&g, R, lo, vs, link, data);
+    oopts op = {step_vox, max_samples, t_near, t_stop, act};
+#pragma omp parallel
+    {
+        otrace tr;
+        trace_alloc(&tr, 256);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < n_rays; ++r) {
+            const int f = frame_of(off, F, r);
+            for (int k = 0; k < 4; ++k) {
+                double gC[3] = {0.0, 0.0, 0.0};
+                double gz = 0.0;
+                if (k < 3) gC[k] = 1.0;
+                else gz = 1.0;
+                ray_backward(&g, &op, flags, c2w + 12 * f, intr + 4 * f, pix[2 * r],
+                             pix[2 * r + 1], gC, gz, &tr, NULL, J + 24 * r + 6 * k);
             }
         }
         trace_free(&tr);
