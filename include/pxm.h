@@ -207,6 +207,35 @@ int pxm_pose_adam(int32_t n_frames, float *c2w, double *grad_pose, double *state
                   float beta1, float beta2, float eps, void *stream);
 
 /*
+ * Gauss-Newton tracking, normal equations (Sec. 5.3, Eq. 12-14 and App. A;
+ * the squared form of Eq. 4, 5 and 11).  Per ray with a valid depth target:
+ * the forward (Eq. 1-3), the residual e = (C-hat - C, z - D) and the pose
+ * Jacobian J [4][6] of (R, G, B, z-depth) with respect to the left se(3)
+ * perturbation (rho, phi), whose row k is the pose gradient of output k
+ * alone.  Per frame f, with w_f = frame_weight[f] and
+ * W = w_f diag(1, 1, 1, lambda_depth):
+ *   gn[f][0..20]  += sum_r (J^T W J)_ij, upper triangle row by row
+ *                    (i <= j: (0,0), (0,1), .., (0,5), (1,1), .., (5,5)),
+ *   gn[f][21..26] += sum_r (J^T W e)_i,
+ *   gn[f][27]     += sum_r e^T W e.
+ * gn is [F][28] float64, accumulated.  opts->depth_loss is not used (the
+ * Gauss-Newton energy is the squared one); PXM_FLAG_POSE_VIEWDIR adds the
+ * exact view-direction term to the rotation columns.
+ */
+int pxm_render_gn(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
+                  const float *tgt_rgb, const float *tgt_depth, const float *frame_weight,
+                  double *gn, void *stream);
+
+/*
+ * Gauss-Newton pose update: per frame, xi = -(H + damping I)^-1 g from the
+ * gn slots of pxm_render_gn (Cholesky in float64), then the left retraction
+ * c2w <- exp(xi^) c2w.  The frame's gn slots are zeroed after they are read;
+ * a frame whose damped H is not positive definite keeps its pose.
+ *   c2w [F][3][4] f32 (in/out), gn [F][28] f64 (in, zeroed).
+ */
+int pxm_pose_gn(int32_t n_frames, float *c2w, double *gn, float damping, void *stream);
+
+/*
  * Mapping update (Sec. 5.4: RMSProp for mapping): one sparse RMSProp step
  * over the vertex records.  A record is touched when any of its 28 entries
  * of grad_data is non-zero; for touched records, entry by entry,

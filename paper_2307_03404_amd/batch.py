@@ -161,19 +161,26 @@ class Autotuner:
 class TrackingGraph:
     """`iters` tracking iterations for all frames of `rays`, captured once.
 
-    Each iteration: fused forward + loss + pose backward (PXM_WANT_POSE) into
-    grad_pose, then pxm_pose_adam, which updates rays.c2w in place and zeroes
-    grad_pose.  losses[it, f] holds the loss of frame f before update it.
+    method "adam": each iteration is the fused forward + loss + pose backward
+    (PXM_WANT_POSE) into grad_pose, then pxm_pose_adam, which updates rays.c2w
+    in place and zeroes grad_pose.  method "gauss-newton": pxm_render_gn
+    accumulates every frame's normal equations, then pxm_pose_gn solves and
+    retracts (and zeroes them).  losses[it, f] holds the energy of frame f
+    before update it.
     """
 
     def __init__(self, grid, rays, opts, tgt_rgb, tgt_depth, frame_weight, iters=20, lr=1e-3,
-                 betas=(0.9, 0.999), eps=1e-8):
+                 betas=(0.9, 0.999), eps=1e-8, method="adam", damping=1e-6):
         dev = grid.data.device
         F = rays.n_frames
+        if method not in ("adam", "gauss-newton"):
+            raise ValueError("method must be 'adam' or 'gauss-newton'")
         self.grid, self.rays, self.opts = grid, rays, opts
         self.tgt = (tgt_rgb, tgt_depth, frame_weight)
         self.iters, self.lr, self.betas, self.eps = iters, lr, betas, eps
+        self.method, self.damping = method, float(damping)
         self.grad_pose = torch.zeros(F, 6, dtype=torch.float64, device=dev)
+        self.gn = torch.zeros(F, pxm.GN_VALUES, dtype=torch.float64, device=dev)
         self.state = torch.zeros(F, 16, dtype=torch.float64, device=dev)
         self.losses = torch.zeros(iters, F, dtype=torch.float64, device=dev)
         self.ws = pxm.new_workspace(grid, rays, opts, pxm.WANT_POSE)
@@ -181,12 +188,19 @@ class TrackingGraph:
 
     def _body(self):
         self.grad_pose.zero_()
+        self.gn.zero_()
         self.losses.zero_()
         for it in range(self.iters):
-            pxm.render_fused(self.grid, self.rays, self.opts, *self.tgt, pxm.WANT_POSE,
-                             loss=self.losses[it], grad_pose=self.grad_pose, ws=self.ws)
-            pxm.pose_adam(self.rays.c2w, self.grad_pose, self.state, self.lr, self.betas[0],
-                          self.betas[1], self.eps)
+            if self.method == "adam":
+                pxm.render_fused(self.grid, self.rays, self.opts, *self.tgt, pxm.WANT_POSE,
+                                 loss=self.losses[it], grad_pose=self.grad_pose, ws=self.ws)
+                pxm.pose_adam(self.rays.c2w, self.grad_pose, self.state, self.lr, self.betas[0],
+                              self.betas[1], self.eps)
+            else:
+                # losses hold the squared (Gauss-Newton) energy of each frame
+                pxm.render_gn(self.grid, self.rays, self.opts, *self.tgt, gn=self.gn)
+                self.losses[it].copy_(self.gn[:, pxm.GN_VALUES - 1])
+                pxm.pose_gn(self.rays.c2w, self.gn, self.damping)
 
     def run_eager(self):
         self._body()
@@ -211,6 +225,7 @@ class TrackingGraph:
         """Restore the starting poses and clear the optimiser state."""
         self.rays.c2w.copy_(c2w)
         self.state.zero_()
+        self.gn.zero_()
 
 
 class MappingLoop:

@@ -275,6 +275,28 @@ int pxm_pose_adam(int32_t n_frames, float* c2w, double* grad_pose, double* state
                                      (hipStream_t)stream), "pose_adam");
 }
 
+int pxm_render_gn(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
+                  const float* tgt_rgb, const float* tgt_depth, const float* frame_weight,
+                  double* gn, void* stream) {
+    PXM_TRY(check_grid(grid));
+    PXM_TRY(check_rays(rays));
+    PXM_TRY(check_opts(opts));
+    if (!gn) return fail(PXM_INVALID_ARGUMENT, "gn is NULL");
+    if (rays->n_rays > 0 && (!tgt_rgb || !tgt_depth || !frame_weight))
+        return fail(PXM_INVALID_ARGUMENT, "targets / frame_weight is NULL");
+    if (rays->n_rays == 0) return PXM_OK;
+    return launched(pxm::launch_gn(kgrid(grid), krays(rays), kopts(opts), tgt_rgb, tgt_depth,
+                                   frame_weight, gn, (hipStream_t)stream), "render_gn");
+}
+
+int pxm_pose_gn(int32_t n_frames, float* c2w, double* gn, float damping, void* stream) {
+    if (n_frames < 1) return fail(PXM_INVALID_ARGUMENT, "n_frames < 1");
+    if (!c2w || !gn) return fail(PXM_INVALID_ARGUMENT, "a required array is NULL");
+    if (!(damping >= 0.f) || !finite(damping))
+        return fail(PXM_INVALID_ARGUMENT, "damping must be finite and >= 0");
+    return launched(pxm::launch_pose_gn(n_frames, c2w, gn, damping, (hipStream_t)stream), "pose_gn");
+}
+
 int pxm_grid_rmsprop(int64_t n_alloc, float* data, float* grad_data, float* state, float lr_density,
                      float lr_sh, float alpha, float eps, void* stream) {
     if (n_alloc < 0 || n_alloc > INT32_MAX) return fail(PXM_INVALID_ARGUMENT, "n_alloc outside [0, 2^31)");

@@ -1,8 +1,11 @@
-// Tracking update: one Adam step per frame on the se(3) tangent of a left,
-// world-frame perturbation, then c2w <- exp(xi^) c2w (FP64 on the device).
-// One lane per frame; the gradient slot is zeroed after it is read so that a
-// captured tracking iteration needs no clearing node.
+// Tracking updates, one lane per frame, in FP64 on the device, each ending in
+// the left retraction c2w <- exp(xi^) c2w:
+//  * Adam on the se(3) tangent of a left, world-frame perturbation;
+//  * a damped Gauss-Newton step from the per-frame normal equations.
+// The consumed gradient or normal-equation slots are zeroed after they are
+// read, so a captured tracking iteration needs no clearing node.
 #include "internal.hpp"
+#include "se3.hpp"
 
 namespace pxm {
 
@@ -25,47 +28,65 @@ __global__ void k_pose_adam(int F, float* __restrict__ c2w, double* __restrict__
         st[6 + j] = v;
         xi[j] = -(double)lr * (m / c1) / (sqrt(v / c2) + (double)eps);
     }
-    // exp of the twist (rho, phi): rotation by Rodrigues, translation V rho
-    const double p0 = xi[3], p1 = xi[4], p2 = xi[5];
-    const double th2 = p0 * p0 + p1 * p1 + p2 * p2, th = sqrt(th2);
-    double A, B, Cc;
-    if (th < 1e-8) {
-        A = 1.0 - th2 / 6.0;
-        B = 0.5 - th2 / 24.0;
-        Cc = 1.0 / 6.0 - th2 / 120.0;
-    } else {
-        A = sin(th) / th;
-        B = (1.0 - cos(th)) / th2;
-        Cc = (th - sin(th)) / (th2 * th);
-    }
-    const double K[3][3] = {{0, -p2, p1}, {p2, 0, -p0}, {-p1, p0, 0}};
-    double K2[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) K2[i][j] = K[i][0] * K[0][j] + K[i][1] * K[1][j] + K[i][2] * K[2][j];
-    double Rx[3][3], V[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            const double I = i == j ? 1.0 : 0.0;
-            Rx[i][j] = I + A * K[i][j] + B * K2[i][j];
-            V[i][j] = I + B * K[i][j] + Cc * K2[i][j];
-        }
-    float* M = c2w + 12 * (int64_t)f;
-    double Mo[3][4];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 4; ++j) Mo[i][j] = M[4 * i + j];
-    for (int i = 0; i < 3; ++i) {
-        for (int j = 0; j < 4; ++j) {
-            double acc = Rx[i][0] * Mo[0][j] + Rx[i][1] * Mo[1][j] + Rx[i][2] * Mo[2][j];
-            if (j == 3) acc += V[i][0] * xi[0] + V[i][1] * xi[1] + V[i][2] * xi[2];
-            M[4 * i + j] = (float)acc;
-        }
-    }
+    se3_apply_left(c2w + 12 * (int64_t)f, xi);
 }
 
 hipError_t launch_adam(int F, float* c2w, double* grad_pose, double* state, float lr, float b1,
                        float b2, float eps, hipStream_t st) {
     const unsigned nb = (unsigned)((F + 63) / 64);
     hipLaunchKernelGGL(k_pose_adam, dim3(nb), dim3(64), 0, st, F, c2w, grad_pose, state, lr, b1, b2, eps);
+    return hipGetLastError();
+}
+
+// gn[f] = (H upper triangle row by row: 21, g: 6, E: 1).  xi = -(H + mu I)^-1 g
+// by Cholesky; a frame whose damped H is not positive definite (no ray saw
+// the grid) keeps its pose.
+__global__ void k_pose_gn(int F, float* __restrict__ c2w, double* __restrict__ gn, float mu) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    double* s = gn + GN_VALUES * (int64_t)f;
+    double L[6][6], rhs[6];
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            L[i][j] = L[j][i] = s[k];
+            ++k;
+        }
+    for (int i = 0; i < 6; ++i) {
+        L[i][i] += (double)mu;
+        rhs[i] = -s[21 + i];
+    }
+    for (int i = 0; i < GN_VALUES; ++i) s[i] = 0.0;
+    // in-place Cholesky: lower triangle of L becomes the factor
+    for (int j = 0; j < 6; ++j) {
+        double d = L[j][j];
+        for (int p = 0; p < j; ++p) d -= L[j][p] * L[j][p];
+        if (!(d > 0.0)) return;
+        d = sqrt(d);
+        L[j][j] = d;
+        for (int i = j + 1; i < 6; ++i) {
+            double v = L[i][j];
+            for (int p = 0; p < j; ++p) v -= L[i][p] * L[j][p];
+            L[i][j] = v / d;
+        }
+    }
+    double y[6], xi[6];
+    for (int i = 0; i < 6; ++i) {
+        double v = rhs[i];
+        for (int p = 0; p < i; ++p) v -= L[i][p] * y[p];
+        y[i] = v / L[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double v = y[i];
+        for (int p = i + 1; p < 6; ++p) v -= L[p][i] * xi[p];
+        xi[i] = v / L[i][i];
+    }
+    se3_apply_left(c2w + 12 * (int64_t)f, xi);
+}
+
+hipError_t launch_pose_gn(int F, float* c2w, double* gn, float mu, hipStream_t st) {
+    const unsigned nb = (unsigned)((F + 63) / 64);
+    hipLaunchKernelGGL(k_pose_gn, dim3(nb), dim3(64), 0, st, F, c2w, gn, mu);
     return hipGetLastError();
 }
 

@@ -36,6 +36,13 @@ hipError_t launch_occupancy(const KGrid& g, uint32_t* occ, hipStream_t st);
 hipError_t launch_adam(int F, float* c2w, double* grad_pose, double* state, float lr, float b1,
                        float b2, float eps, hipStream_t st);
 
+// Gauss-Newton slots per frame: H upper triangle (21), g (6), E (1).
+constexpr int GN_VALUES = 28;
+
+hipError_t launch_gn(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,
+                     const float* tgt_depth, const float* frame_weight, double* gn, hipStream_t st);
+hipError_t launch_pose_gn(int F, float* c2w, double* gn, float mu, hipStream_t st);
+
 hipError_t launch_rmsprop(int64_t n, float* data, float* grad, float* avg, float lr_d, float lr_sh,
                           float alpha, float eps, hipStream_t st);
 

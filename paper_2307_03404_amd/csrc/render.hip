@@ -325,6 +325,175 @@ __device__ __forceinline__ void pose_six(const Ray& ray, const PoseAcc& pa, doub
 }
 
 // ---------------------------------------------------------------------------
+// Gauss-Newton tracking: per-ray pose Jacobian of (R, G, B, z-depth)
+// ---------------------------------------------------------------------------
+
+// Pose accumulators of the four outputs (colour channels, then z-depth).
+struct JacAcc {
+    float go[4][3];
+    float gd[4][3];
+    float gv[4][3];
+};
+
+// One occupied sample of the Jacobian march: row k is the pose gradient of
+// output k alone (unit upstream on it), so the sample's factors are those of
+// Eq. 8-10 with gC = e_k (colour rows) or dL/d range = 1/s (depth row).
+template <bool VIEW>
+__device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op, const Ray& ray,
+                                                const float Y[9], const float GY[9][3],
+                                                const Sample& s, const float Chat[3], float Dhat,
+                                                BwdState& st, JacAcc& ja) {
+    int idx[8];
+    if (load_links(g, s.base, idx) == 0) return;
+    CornerVals cv;
+    float ev[8][3][3];
+    if (VIEW) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            cv.sig[b] = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cv.e[b][c] = 0.f;
+                ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
+            }
+            if (idx[b] >= 0) {
+                float rec[REC];
+                load_record(g.data, idx[b], rec);
+                cv.sig[b] = rec[0];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+                    for (int kk = 0; kk < 9; ++kk) {
+                        const float sh = rec[1 + 9 * c + kk];
+                        acc = fmaf(Y[kk], sh, acc);
+                        a0 = fmaf(GY[kk][0], sh, a0);
+                        a1 = fmaf(GY[kk][1], sh, a1);
+                        a2 = fmaf(GY[kk][2], sh, a2);
+                    }
+                    cv.e[b][c] = acc;
+                    ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
+                }
+            }
+        }
+    } else {
+        load_corner_vals(g, idx, Y, cv);
+    }
+    float w[8];
+    trilinear_weights(s.f, w);
+    float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        sr = fmaf(w[b], cv.sig[b], sr);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
+    }
+    if (!(sr > 0.f)) return;
+    const float delta = op.step_vox;
+    const float x = sr * delta;
+    const float wt = st.T * (-expm1f(-x));
+    st.L += (double)x;
+    const float Tn = trans_of(st.L);
+    float c[3], dact[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        c[ch] = act_fwd(op.act, sc[ch]);
+        dact[ch] = act_bwd(op.act, sc[ch]) * wt;
+        st.A[ch] = fmaf(wt, c[ch], st.A[ch]);
+    }
+    st.AD = fmaf(wt, s.t, st.AD);
+    // per-output density factor (Eq. 9 / Eq. 10) and colour factor (Eq. 8)
+    float gsig[4], gsc[4];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        gsig[ch] = delta * (c[ch] * Tn - Chat[ch] + st.A[ch]);
+        gsc[ch] = dact[ch];
+    }
+    gsig[3] = delta * (s.t * Tn - Dhat + st.AD) / ray.s;
+    gsc[3] = 0.f;
+    const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
+    const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
+    const float inv_vs = (float)g.inv_vs;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float h[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            h[b] = gsig[k] * cv.sig[b] + (k < 3 ? gsc[k] * cv.e[b][k < 3 ? k : 0] : 0.f);
+        const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
+                       + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
+        const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
+                       + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
+        const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
+                       + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
+        const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ja.go[k][a] += gp[a];
+            ja.gd[k][a] = fmaf(s.t, gp[a], ja.gd[k][a]);
+        }
+        if (VIEW && k < 3) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float acc = 0.f;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) acc = fmaf(w[b], gsc[k] * ev[b][k < 3 ? k : 0][a], acc);
+                ja.gv[k][a] += acc;
+            }
+        }
+    }
+    st.T = Tn;
+}
+
+// Jacobian rows J[k] = (g_o, o x g_o + d x g_d (+ d x g_view)) of one ray.
+template <bool VIEW>
+__device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, const Ray& ray,
+                                             const float Y[9], int n, const float Chat[3],
+                                             float Dhat, float J[4][6]) {
+    float GY[9][3];
+    if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
+    BwdState st = {{0.f, 0.f, 0.f}, 0.f, 1.f, 0.0};
+    JacAcc ja;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ja.go[k][a] = ja.gd[k][a] = ja.gv[k][a] = 0.f;
+    const int64_t ke = ray.k_first + (n > 0 ? n : 0);
+    int64_t k = ray.k_first;
+    while (k < ke) {
+        Sample s;
+        if (!sample_at(g, ray, k, s)) break;
+        if (g.occ0) {
+            if (brick_empty(g, s.c)) {
+                const int64_t nxt = brick_exit(g, ray, k, s.c);
+                k = nxt < ke ? nxt : ke;
+                continue;
+            }
+            if (!cell_occupied(g, s.c)) {
+                ++k;
+                continue;
+            }
+        }
+        jacobian_sample<VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
+        ++k;
+    }
+    const float* o = ray.o;
+    const float* d = ray.d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float gd[3] = {ja.gd[q][0], ja.gd[q][1], ja.gd[q][2]};
+        if (VIEW) { gd[0] += ja.gv[q][0]; gd[1] += ja.gv[q][1]; gd[2] += ja.gv[q][2]; }
+        const float* go = ja.go[q];
+        J[q][0] = go[0];
+        J[q][1] = go[1];
+        J[q][2] = go[2];
+        J[q][3] = (o[1] * go[2] - o[2] * go[1]) + (d[1] * gd[2] - d[2] * gd[1]);
+        J[q][4] = (o[2] * go[0] - o[0] * go[2]) + (d[2] * gd[0] - d[0] * gd[2]);
+        J[q][5] = (o[0] * go[1] - o[1] * go[0]) + (d[0] * gd[1] - d[1] * gd[0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 
@@ -512,6 +681,65 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
     }
 }
 
+// Gauss-Newton normal equations: per ray, forward, 4-residual and Jacobian;
+// per frame, H = sum w J^T W J (upper triangle), g = sum w J^T W e and the
+// error E, with W = diag(1, 1, 1, lambda_depth) over rays with a valid depth.
+template <bool VIEW>
+__global__ void __launch_bounds__(256) k_gn(KGrid g, KRays rs, KOpts op,
+                                            const float* __restrict__ tgt_rgb,
+                                            const float* __restrict__ tgt_depth,
+                                            const float* __restrict__ fw,
+                                            double* __restrict__ gn) {
+    const int64_t r = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const bool inr = r < rs.n;
+    int f = 0;
+    bool valid = false;
+    double vals[GN_VALUES];
+#pragma unroll
+    for (int i = 0; i < GN_VALUES; ++i) vals[i] = 0.0;
+    if (inr) {
+        f = frame_of(rs.off, rs.F, r);
+        Ray ray;
+        setup_ray(g, rs, op, r, f, ray);
+        float Y[9];
+        sh9(ray.d[0], ray.d[1], ray.d[2], Y);
+        FwdResult fr;
+        ray_forward(g, op, ray, Y, fr);
+        const float Dt = tgt_depth[r];
+        valid = isfinite(Dt) && Dt > 0.f;
+        if (valid) {
+            const float e[4] = {fr.C[0] - tgt_rgb[3 * r], fr.C[1] - tgt_rgb[3 * r + 1],
+                                fr.C[2] - tgt_rgb[3 * r + 2], fr.D / ray.s - Dt};
+            float J[4][6];
+            ray_jacobian<VIEW>(g, op, ray, Y, fr.n, fr.C, fr.D, J);
+            const double wf = (double)fw[f];
+            const double Wk[4] = {wf, wf, wf, wf * (double)op.lambda_d};
+            int q = 0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int j = i; j < 6; ++j) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) acc += Wk[k] * (double)J[k][i] * (double)J[k][j];
+                    vals[q++] = acc;
+                }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc += Wk[k] * (double)J[k][i] * (double)e[k];
+                vals[21 + i] = acc;
+            }
+            double E = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) E += Wk[k] * (double)e[k] * (double)e[k];
+            vals[27] = E;
+        }
+    }
+    seg_sum_atomic<GN_VALUES>(f, valid, vals, gn);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -626,6 +854,18 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
     } else {
         fused_go<false, false, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gn(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,
+                     const float* tgt_depth, const float* frame_weight, double* gn, hipStream_t st) {
+    const dim3 grid(blocks_for(rs.n, 256)), block(256);
+    if (op.flags & 1)
+        hipLaunchKernelGGL((k_gn<true>), grid, block, 0, st, g, rs, op, tgt_rgb, tgt_depth,
+                           frame_weight, gn);
+    else
+        hipLaunchKernelGGL((k_gn<false>), grid, block, 0, st, g, rs, op, tgt_rgb, tgt_depth,
+                           frame_weight, gn);
     return hipGetLastError();
 }
 

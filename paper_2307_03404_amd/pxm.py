@@ -55,6 +55,7 @@ _lib = None
 _lock = threading.Lock()
 EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
            "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_grid_rmsprop",
+           "pxm_render_gn", "pxm_pose_gn",
            "pxm_workspace_bytes",
            "pxm_occupancy_words", "pxm_build_occupancy",
            "pxm_set_tuning", "pxm_get_tuning", "pxm_status_string", "pxm_last_error",
@@ -82,6 +83,8 @@ def lib():
         L.pxm_render_fused.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P, sz, P]
         L.pxm_pose_adam.argtypes = [i32, P, P, P, f32, f32, f32, f32, P]
         L.pxm_grid_rmsprop.argtypes = [i64, P, P, P, f32, f32, f32, f32, P]
+        L.pxm_render_gn.argtypes = [G, R, O, P, P, P, P, P]
+        L.pxm_pose_gn.argtypes = [i32, P, P, f32, P]
         L.pxm_occupancy_words.argtypes = [G]
         L.pxm_occupancy_words.restype = sz
         L.pxm_build_occupancy.argtypes = [G, P, sz, P]
@@ -351,6 +354,46 @@ def pose_adam(c2w, grad_pose, state, lr, beta1=0.9, beta2=0.999, eps=1e-8, strea
     _check("pose_adam", lib().pxm_pose_adam(F, _ptr(c2w), _ptr(grad_pose), _ptr(state), float(lr),
                                             float(beta1), float(beta2), float(eps),
                                             _stream(stream)))
+
+
+GN_VALUES = 28
+
+
+def render_gn(grid, rays, opts, tgt_rgb, tgt_depth, frame_weight, gn=None, stream=None):
+    """Gauss-Newton normal equations per frame, accumulated into gn f64[F, 28]
+    (H upper triangle 21, g 6, E 1)."""
+    n, F = rays.n_rays, rays.n_frames
+    dev = grid.data.device
+    _need(tgt_rgb, "tgt_rgb", torch.float32, (n, 3))
+    _need(tgt_depth, "tgt_depth", torch.float32, (n,))
+    _need(frame_weight, "frame_weight", torch.float32, (F,))
+    if gn is None:
+        gn = torch.zeros(F, GN_VALUES, dtype=torch.float64, device=dev)
+    _need(gn, "gn", torch.float64, (F, GN_VALUES))
+    g, r, o = grid.struct(), rays.struct(), opts_struct(opts)
+    _check("render_gn", lib().pxm_render_gn(C.byref(g), C.byref(r), C.byref(o), _ptr(tgt_rgb),
+                                            _ptr(tgt_depth), _ptr(frame_weight), _ptr(gn),
+                                            _stream(stream)))
+    return gn
+
+
+def pose_gn(c2w, gn, damping=1e-6, stream=None):
+    """Damped Gauss-Newton pose step per frame (in place); zeroes gn."""
+    F = int(c2w.shape[0])
+    _need(c2w, "c2w", torch.float32, (F, 3, 4))
+    _need(gn, "gn", torch.float64, (F, GN_VALUES))
+    _check("pose_gn", lib().pxm_pose_gn(F, _ptr(c2w), _ptr(gn), float(damping), _stream(stream)))
+
+
+def gn_unpack(gn):
+    """(H [F,6,6], g [F,6], E [F]) from the packed rows of render_gn."""
+    gn = torch.as_tensor(gn)
+    F = gn.shape[0]
+    H = torch.zeros(F, 6, 6, dtype=gn.dtype, device=gn.device)
+    iu = torch.triu_indices(6, 6)
+    H[:, iu[0], iu[1]] = gn[:, :21]
+    H[:, iu[1], iu[0]] = gn[:, :21]
+    return H, gn[:, 21:27], gn[:, 27]
 
 
 def grid_rmsprop(data, grad_data, state, lr_density, lr_sh, alpha=0.95, eps=1e-8, stream=None):
