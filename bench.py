@@ -131,8 +131,9 @@ def tracking_bench(wl, g, r, trgb, tdep, fw, args):
     from paper_2307_03404_amd.batch import TrackingGraph
     n, F = wl.rays.n_rays, wl.rays.n_frames
     iters = int(wl.meta.get("iters", 20))
+    method = "gauss-newton" if args.gauss_newton else "adam"
     c2w0 = r.c2w.clone()
-    tg = TrackingGraph(g, r, wl.opts, trgb, tdep, fw, iters=iters, lr=1e-3)
+    tg = TrackingGraph(g, r, wl.opts, trgb, tdep, fw, iters=iters, lr=1e-3, method=method)
     tg.run_eager()                                   # warm-up and lazy set-up outside capture
     torch.cuda.synchronize()
     tg.reset(c2w0)
@@ -163,19 +164,24 @@ def tracking_bench(wl, g, r, trgb, tdep, fw, args):
                      grad_pose=gp, stats=stats, ws=ws)
     torch.cuda.synchronize()
     bytes_launch = alg_bytes(stats.cpu().numpy(), n, F, pxm.WANT_POSE)
+    gn = torch.zeros(F, pxm.GN_VALUES, dtype=torch.float64, device=g.data.device)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(10):
-        pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, pxm.WANT_POSE, loss=loss, grad_pose=gp,
-                         ws=ws)
+        if args.gauss_newton:
+            pxm.render_gn(g, r, wl.opts, trgb, tdep, fw, gn=gn)
+        else:
+            pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, pxm.WANT_POSE, loss=loss,
+                             grad_pose=gp, ws=ws)
     e1.record()
     torch.cuda.synchronize()
     kern_ms = e0.elapsed_time(e1) / 10
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
     block, variant = pxm.get_tuning()
+    what = ("fwd + residual + 4x6 pose Jacobian + per-frame normal equations + damped "
+            "Gauss-Newton step" if args.gauss_newton else "fwd + loss + se(3) pose bwd + Adam")
     out = {
-        "metric": "tracking rays/s (fwd + loss + se(3) pose bwd + Adam, all frames, "
-                  f"{iters} iterations in one hipGraph)",
+        "metric": f"tracking rays/s ({what}, all frames, {iters} iterations in one hipGraph)",
         "value": n * iters * args.steps / elapsed, "unit": "rays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -185,7 +191,8 @@ def tracking_bench(wl, g, r, trgb, tdep, fw, args):
                    "block": block, "variant": variant},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_fused<false,true,false>", "kernel_ms": kern_ms,
+                     "kernel": "k_gn<false>" if args.gauss_newton else "k_fused<false,true,false>",
+                     "kernel_ms": kern_ms,
                      "alg_bytes_per_launch": bytes_launch},
         "graph_ms_median": graph_ms,
         "loss_first_last_iteration": [first, last],
@@ -271,6 +278,8 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--compare-per-frame", action="store_true",
                     help="time one batched fused launch against per-frame launches instead")
+    ap.add_argument("--gauss-newton", action="store_true",
+                    help="tracking workloads: Gauss-Newton iterations instead of Adam")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (for scaling HBM byte counters)")
     args = ap.parse_args()
