@@ -240,7 +240,7 @@ template <bool GRID, bool POSE, bool VIEW>
 __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, const Ray& ray,
                                              const float Y[9], int n, const float Chat[3],
                                              float Dhat, const float gC[3], float gDr,
-                                             float* __restrict__ grad, const WaveCache& wc,
+                                             float* __restrict__ grad, const WaveStage& wc,
                                              PoseAcc& pa) {
     float GY[9][3];
     if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
@@ -280,7 +280,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             if (work)
                 have = backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
                                                    pa, idx, w, gsig, gs);
-            scatter_merged(have, s.base, s.c, idx, w, gsig, gs, Y, wc, grad);
+            scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
             ++k;
         }
     } else {
@@ -525,12 +525,8 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
                                                   float* __restrict__ grad,
                                                   double* __restrict__ grad_pose) {
     extern __shared__ float smem[];
-    WaveCache wc{nullptr, nullptr};
-    if (GRID) {
-        wc = wave_cache(smem);
-        cache_init(wc);
-        __syncthreads();
-    }
+    WaveStage wc{nullptr, nullptr, nullptr};
+    if (GRID) wc = wave_stage(smem);
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = r < rs.n;
     int f = 0;
@@ -560,7 +556,6 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
         }
     }
     ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, n, Chat, Dhat, gC, gDr, grad, wc, pa);
-    if (GRID) cache_flush(wc, grad);
     if (POSE) {
         double six[6] = {0, 0, 0, 0, 0, 0};
         if (active) pose_six<VIEW>(ray, pa, six);
@@ -582,12 +577,8 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
                                                unsigned* __restrict__ ws, int persistent) {
     __shared__ int64_t s_tile;
     extern __shared__ float smem[];
-    WaveCache wc{nullptr, nullptr};
-    if (GRID) {
-        wc = wave_cache(smem);
-        cache_init(wc);
-        __syncthreads();
-    }
+    WaveStage wc{nullptr, nullptr, nullptr};
+    if (GRID) wc = wave_stage(smem);
     const int64_t n_tiles = (rs.n + blockDim.x - 1) / blockDim.x;
     // Persistent form: workgroups take tiles in order from one queue counter
     // (ws[0]), so the tiles in flight at any time are neighbours in the
@@ -669,7 +660,6 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
         }
         if (!persistent) break;
     }
-    if (GRID) cache_flush(wc, grad);
     if (persistent && threadIdx.x == 0) {
         // the last workgroup to finish re-arms the queue for the next launch
         __threadfence();
@@ -762,7 +752,7 @@ hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, con
     const dim3 grid(blocks_for(rs.n, 256)), block(256);
     const bool view = (op.flags & 1) != 0;
     if (grad_data && !grad_pose) {
-        // one wave per workgroup: the per-wave LDS (cache + MFMA staging) is ~24 KB
+        // one wave per workgroup: each wave stages its MFMA operands in ~19 KB of LDS
         const size_t lds = WAVE_LDS_FLOATS * sizeof(float);
         hipLaunchKernelGGL((k_backward<true, false, false>), dim3(blocks_for(rs.n, WAVE)),
                            dim3(WAVE), lds, st, g, rs, op, rgb,

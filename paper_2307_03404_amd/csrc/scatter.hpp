@@ -11,9 +11,11 @@
 // a small dense contraction over the 64 lanes.  Up to four groups (32 rows)
 // are contracted per pass on the matrix cores with 32 FP32 MFMA 32x32x2
 // instructions (K = 2 lanes each); W and G are staged in LDS in the operand
-// order the instruction reads.  The 32 x 28 totals are added into a per-wave
-// write-combining cache of vertex records in LDS, which writes back to HBM
-// with atomics only on eviction and when the wave ends.
+// order the instruction reads.  The 32 x 28 totals go to HBM with atomics,
+// each instruction covering the two contiguous 112-byte records of corners r
+// and 4 + r of a group.  (A per-wave LDS write-combining cache in front of
+// the atomics saved HBM writes but its 7 KB per wave lowered occupancy from
+// 8 to 6 waves per CU, which cost more than it saved.)
 #pragma once
 
 #include "kcommon.hpp"
@@ -23,53 +25,23 @@ namespace pxm {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
-// per-wave LDS: write-combining cache + MFMA operand staging
+// per-wave LDS: MFMA operand staging and the lanes' trilinear weights
 // ---------------------------------------------------------------------------
 
-constexpr int CACHE_SLOTS = 64;
 constexpr int STAGE_LD = 33;                              // padded row: conflict-free reads
 constexpr int STAGE_FLOATS = 64 * STAGE_LD;               // one operand: 64 rows (h*32 + i)
-constexpr int WAVE_LDS_FLOATS = CACHE_SLOTS * (REC + 1) + 2 * STAGE_FLOATS + WAVE * 8;
+constexpr int WAVE_LDS_FLOATS = 2 * STAGE_FLOATS + WAVE * 8;
 
-struct WaveCache {
-    int* key;       // [CACHE_SLOTS], -1 = free
-    float* data;    // [CACHE_SLOTS][REC]
+struct WaveStage {
     float* sa;      // staged W operand
     float* sb;      // staged G operand
     float* sw;      // [WAVE][8] each lane's trilinear weights (16-byte aligned)
 };
 
-__device__ __forceinline__ WaveCache wave_cache(float* smem) {
+__device__ __forceinline__ WaveStage wave_stage(float* smem) {
     const int w = threadIdx.x / WAVE;
-    float* base = smem + (size_t)w * WAVE_LDS_FLOATS;
-    float* data = base + CACHE_SLOTS;
-    float* sa = data + CACHE_SLOTS * REC;
-    return WaveCache{reinterpret_cast<int*>(base), data, sa, sa + STAGE_FLOATS, sa + 2 * STAGE_FLOATS};
-}
-
-// Mark every slot free; the caller synchronises the workgroup afterwards.
-__device__ __forceinline__ void cache_init(const WaveCache& wc) {
-    for (int s = lane_id(); s < CACHE_SLOTS; s += WAVE) wc.key[s] = -1;
-}
-
-// Slot of lattice vertex (x, y, z): its parity bits select 3 of the 6 slot bits,
-// so the 8 corners of any cell land in 8 different slots.
-__device__ __forceinline__ int vertex_slot(int x, int y, int z) {
-    const uint32_t h = ((uint32_t)(x >> 1) * 73856093u) ^ ((uint32_t)(y >> 1) * 19349663u)
-                     ^ ((uint32_t)(z >> 1) * 83492791u);
-    return (int)(((x & 1) << 5) | ((y & 1) << 4) | ((z & 1) << 3) | ((h >> 13) & 7));
-}
-
-// Write every occupied slot back to HBM and free it.
-__device__ __forceinline__ void cache_flush(const WaveCache& wc, float* __restrict__ grad) {
-    const int lane = lane_id();
-#pragma unroll 1
-    for (int s = 0; s < CACHE_SLOTS; ++s) {
-        const int cur = wc.key[s];
-        if (cur < 0) continue;
-        if (lane < REC) unsafeAtomicAdd(grad + (int64_t)cur * REC + lane, wc.data[s * REC + lane]);
-        wc.key[s] = -1;
-    }
+    float* sa = smem + (size_t)w * WAVE_LDS_FLOATS;
+    return WaveStage{sa, sa + STAGE_FLOATS, sa + 2 * STAGE_FLOATS};
 }
 
 // Staging addresses.  Operand element for MFMA step c (lanes 2c and 2c+1) and
@@ -83,19 +55,18 @@ __device__ __forceinline__ int stage_at(int i, int ray_lane) {
 // ---------------------------------------------------------------------------
 
 // A pass whose groups cover at most this many lanes is summed lane by lane
-// (scalar broadcast of each member's weights) instead of on the matrix cores,
-// and written out without the cache: rays of a sparse pixel subset rarely
-// share a cell, and one MFMA pass plus its cache update costs as much as
-// about this many broadcast members.
+// (broadcast of each member's weights and gradient row from LDS) instead of
+// on the matrix cores: rays of a sparse pixel subset rarely share a cell, and
+// one MFMA pass costs about as much as this many broadcast members.
 constexpr int SMALL_PASS_LANES = 16;
 
 // Gradient of one sample: dL/d sigma_raw (gsig) and dL/ds_c (gs[c]) to be
-// spread over the corners of cell `cell` (link base `key`, corner ids idx[],
-// trilinear weights w[]).  Must be reached by every lane of the wave.
-__device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int cell[3],
-                                               const int idx[8], const float w[8], float gsig,
-                                               const float gs[3], const float Y[9],
-                                               const WaveCache& wc, float* __restrict__ grad) {
+// spread over the corners of the cell with link base `key` (corner ids
+// idx[], trilinear weights w[]).  Must be reached by every lane of the wave.
+__device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int idx[8],
+                                               const float w[8], float gsig, const float gs[3],
+                                               const float Y[9], const WaveStage& wc,
+                                               float* __restrict__ grad) {
     unsigned long long pending = __ballot(have);
     if (!pending) return;
     const int lane = lane_id();
@@ -158,10 +129,7 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
             for (int c = 0; c < 32; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[c], pb[c], acc, 0, 0, 0);
         } else {
             // the same totals in the same register layout, member by member:
-            // lane (h, j) adds w_{4h+r}(s) * G[s][j] into row 4h + r of group g;
-            // then straight to HBM (each atomic instruction covers the two
-            // 112-byte records of corners r and 4 + r), bypassing the cache
-            // that small groups would mostly evict from
+            // lane (h, j) adds w_{4h+r}(s) * G[s][j] into row 4h + r of group g
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 if (g >= ng) continue;                      // wave-uniform
@@ -176,49 +144,19 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
                     acc[4 * g + 2] = fmaf(wv.z, gv, acc[4 * g + 2]);
                     acc[4 * g + 3] = fmaf(wv.w, gv, acc[4 * g + 3]);
                 }
-                const int ld = leader[g];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int id0 = __builtin_amdgcn_readlane(idx[r], ld);
-                    const int id1 = __builtin_amdgcn_readlane(idx[4 + r], ld);
-                    const int vid = h ? id1 : id0;
-                    if (vid >= 0 && j < REC) unsafeAtomicAdd(grad + (int64_t)vid * REC + j, acc[4 * g + r]);
-                }
             }
-            continue;
         }
-        // accumulator r holds row 8*(r/4) + 4*h + r%4 = group r/4, corner 4*h + r%4, column j
+        // accumulator r holds row 8*(r/4) + 4*h + r%4 = group r/4, corner 4*h + r%4,
+        // field j: one atomic instruction per r covers corners r%4 and 4 + r%4
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int g = r >> 2;
             if (g >= ng) continue;                          // wave-uniform
             const int ld = leader[g];
-            const int b0 = r & 3, b1 = 4 + (r & 3);
-            const int id0 = __builtin_amdgcn_readlane(idx[b0], ld);
-            const int id1 = __builtin_amdgcn_readlane(idx[b1], ld);
-            const int cx = __builtin_amdgcn_readlane(cell[0], ld);
-            const int cy = __builtin_amdgcn_readlane(cell[1], ld);
-            const int cz = __builtin_amdgcn_readlane(cell[2], ld);
-            const int b = h ? b1 : b0;
+            const int id0 = __builtin_amdgcn_readlane(idx[r & 3], ld);
+            const int id1 = __builtin_amdgcn_readlane(idx[4 + (r & 3)], ld);
             const int vid = h ? id1 : id0;
-            const int slot = vertex_slot(cx + ((b >> 2) & 1), cy + ((b >> 1) & 1), cz + (b & 1));
-            const int cur = wc.key[slot];
-            if (vid >= 0) {
-                if (j < REC) {
-                    float* p = wc.data + slot * REC + j;
-                    const float old = *p;
-                    if (cur == vid) {
-                        *p = old + acc[r];
-                    } else {
-                        if (cur >= 0) unsafeAtomicAdd(grad + (int64_t)cur * REC + j, old);
-                        *p = acc[r];
-                    }
-                }
-                wc.key[slot] = vid;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (vid >= 0 && j < REC) unsafeAtomicAdd(grad + (int64_t)vid * REC + j, acc[r]);
         }
     }
 }
