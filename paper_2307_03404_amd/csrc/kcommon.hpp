@@ -372,12 +372,6 @@ __device__ __forceinline__ int load_links(const KGrid& g, int64_t base, int idx[
     return n;
 }
 
-// Per-corner density and colour-channel SH dot products with the ray's basis.
-struct CornerVals {
-    float sig[8];
-    float e[8][3];
-};
-
 __device__ __forceinline__ void load_record(const float* __restrict__ data, int id, float rec[REC]) {
     const float4* p = reinterpret_cast<const float4*>(data + (int64_t)id * REC);
 #pragma unroll
@@ -387,23 +381,72 @@ __device__ __forceinline__ void load_record(const float* __restrict__ data, int 
     }
 }
 
-__device__ __forceinline__ void load_corner_vals(const KGrid& g, const int idx[8], const float Y[9],
-                                                 CornerVals& cv) {
+// The fields of one sample, interpolated (and, for the pose, differentiated
+// in space: Eq. 16 / Appendix A) corner by corner as the records arrive, so
+// no per-corner values stay live.  Colour entries are the SH expansions
+// s_c = sum_k Y_k SH_{c,k} of the ray's basis.
+struct Interp {
+    float sig;          // raw density
+    float s[3];         // colour pre-activations
+    float dsig[3];      // d sig / dq_a (voxel units)           GRAD only
+    float ds[3][3];     // d s_c / dq_a                          GRAD only
+    float ev[3][3];     // sum_b w_b sum_k dY_k/dd_a SH_{b,c,k}  VIEW only
+};
+
+template <bool GRAD, bool VIEW>
+__device__ __forceinline__ void gather_interp(const KGrid& g, const int idx[8], const float Y[9],
+                                              const float GY[9][3], const float f[3], Interp& v) {
+    v.sig = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v.s[c] = 0.f;
+        v.dsig[c] = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v.ds[c][a] = v.ev[c][a] = 0.f;
+    }
+    const float x1 = f[0], x0 = 1.0f - f[0];
+    const float y1 = f[1], y0 = 1.0f - f[1];
+    const float z1 = f[2], z0 = 1.0f - f[2];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        cv.sig[b] = 0.0f;
-        cv.e[b][0] = cv.e[b][1] = cv.e[b][2] = 0.0f;
-        if (idx[b] >= 0) {
-            float rec[REC];
-            load_record(g.data, idx[b], rec);
-            cv.sig[b] = rec[0];
+        if (idx[b] < 0) continue;
+        const int bx = (b >> 2) & 1, by = (b >> 1) & 1, bz = b & 1;
+        const float wx = bx ? x1 : x0, wy = by ? y1 : y0, wz = bz ? z1 : z0;
+        const float w = (wx * wy) * wz;
+        float rec[REC];
+        load_record(g.data, idx[b], rec);
+        float e[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float acc = 0.0f;
+        for (int c = 0; c < 3; ++c) {
+            float acc = 0.0f;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) acc = fmaf(Y[k], rec[1 + 9 * c + k], acc);
-                cv.e[b][c] = acc;
+            for (int k = 0; k < 9; ++k) acc = fmaf(Y[k], rec[1 + 9 * c + k], acc);
+            e[c] = acc;
+        }
+        v.sig = fmaf(w, rec[0], v.sig);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v.s[c] = fmaf(w, e[c], v.s[c]);
+        if (GRAD) {
+            // d w_b / dq = (+-wy wz, wx +-wz... ) with the sign of each offset
+            const float dw[3] = {(bx ? 1.f : -1.f) * wy * wz, wx * (by ? 1.f : -1.f) * wz,
+                                 wx * wy * (bz ? 1.f : -1.f)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                v.dsig[a] = fmaf(dw[a], rec[0], v.dsig[a]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v.ds[c][a] = fmaf(dw[a], e[c], v.ds[c][a]);
             }
+        }
+        if (VIEW) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) acc = fmaf(GY[k][a], rec[1 + 9 * c + k], acc);
+                    v.ev[c][a] = fmaf(w, acc, v.ev[c][a]);
+                }
         }
     }
 }

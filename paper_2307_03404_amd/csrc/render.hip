@@ -61,18 +61,9 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
             int idx[8];
             const int na = load_links(g, s.base, idx);
             if (na == 0) continue;
-            CornerVals cv;
-            load_corner_vals(g, idx, Y, cv);
-            float w[8];
-            trilinear_weights(s.f, w);
-            float sr = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                sr = fmaf(w[b], cv.sig[b], sr);
-                s0 = fmaf(w[b], cv.e[b][0], s0);
-                s1 = fmaf(w[b], cv.e[b][1], s1);
-                s2 = fmaf(w[b], cv.e[b][2], s2);
-            }
+            Interp v;
+            gather_interp<false, false>(g, idx, Y, nullptr, s.f, v);
+            const float sr = v.sig, s0 = v.s[0], s1 = v.s[1], s2 = v.s[2];
             ++occ;
             occc += na;
             if (!(sr > 0.f)) continue;
@@ -121,48 +112,10 @@ __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op,
                                                 PoseAcc& pa, int idx[8], float w[8], float& gsig,
                                                 float gs[3]) {
     if (load_links(g, s.base, idx) == 0) return false;
-    CornerVals cv;
-    float ev[8][3][3];      // per corner, channel: sum_k dY_k/dd * SH_k (VIEW only)
-    if (VIEW) {
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            cv.sig[b] = 0.f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                cv.e[b][c] = 0.f;
-                ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
-            }
-            if (idx[b] >= 0) {
-                float rec[REC];
-                load_record(g.data, idx[b], rec);
-                cv.sig[b] = rec[0];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-                    for (int kk = 0; kk < 9; ++kk) {
-                        const float sh = rec[1 + 9 * c + kk];
-                        acc = fmaf(Y[kk], sh, acc);
-                        a0 = fmaf(GY[kk][0], sh, a0);
-                        a1 = fmaf(GY[kk][1], sh, a1);
-                        a2 = fmaf(GY[kk][2], sh, a2);
-                    }
-                    cv.e[b][c] = acc;
-                    ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
-                }
-            }
-        }
-    } else {
-        load_corner_vals(g, idx, Y, cv);
-    }
+    Interp v;
+    gather_interp<POSE, POSE && VIEW>(g, idx, Y, GY, s.f, v);
     trilinear_weights(s.f, w);
-    float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        sr = fmaf(w[b], cv.sig[b], sr);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
-    }
+    const float sr = v.sig;
     if (!(sr > 0.f)) return false;      // sigma = 0: no light, zero gradient (ReLU)
     const float delta = op.step_vox;
     const float x = sr * delta;
@@ -172,8 +125,8 @@ __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op,
     float c[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        c[ch] = act_fwd(op.act, sc[ch]);
-        gs[ch] = act_bwd(op.act, sc[ch]) * wt * gC[ch];      // Eq. 8 through act
+        c[ch] = act_fwd(op.act, v.s[ch]);
+        gs[ch] = act_bwd(op.act, v.s[ch]) * wt * gC[ch];      // Eq. 8 through act
         st.A[ch] = fmaf(wt, c[ch], st.A[ch]);
     }
     st.AD = fmaf(wt, s.t, st.AD);
@@ -183,36 +136,16 @@ __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op,
                   + gC[2] * (c[2] * Tn - Chat[2] + st.A[2])
                   + gDr * (s.t * Tn - Dhat + st.AD));
     if (POSE) {
-        // Appendix A: grad of the interpolant = sum_b grad(w_b) v_b; fold the
-        // sample's upstream gradients into one value per corner first.
-        float h[8];
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-            h[b] = gsig * cv.sig[b] + gs[0] * cv.e[b][0] + gs[1] * cv.e[b][1] + gs[2] * cv.e[b][2];
-        const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
-        const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
-        const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
-                       + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
-        const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
-                       + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
-        const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
-                       + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
+        // Appendix A: the spatial gradient of the interpolant, dL/dp =
+        // gsig grad(sigma) + sum_c gs_c grad(s_c), in world units
         const float inv_vs = (float)g.inv_vs;
-        const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            pa.go[a] += gp[a];
-            pa.gd[a] = fmaf(s.t, gp[a], pa.gd[a]);
-        }
-        if (VIEW) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                float acc = 0.f;
-#pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    acc = fmaf(w[b], gs[0] * ev[b][0][a] + gs[1] * ev[b][1][a] + gs[2] * ev[b][2][a], acc);
-                pa.gv[a] += acc;
-            }
+            const float gp = (gsig * v.dsig[a] + gs[0] * v.ds[0][a] + gs[1] * v.ds[1][a]
+                              + gs[2] * v.ds[2][a]) * inv_vs;
+            pa.go[a] += gp;
+            pa.gd[a] = fmaf(s.t, gp, pa.gd[a]);
+            if (VIEW) pa.gv[a] += gs[0] * v.ev[0][a] + gs[1] * v.ev[1][a] + gs[2] * v.ev[2][a];
         }
     }
     st.T = Tn;
@@ -345,49 +278,9 @@ __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op,
                                                 BwdState& st, JacAcc& ja) {
     int idx[8];
     if (load_links(g, s.base, idx) == 0) return;
-    CornerVals cv;
-    float ev[8][3][3];
-    if (VIEW) {
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            cv.sig[b] = 0.f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                cv.e[b][c] = 0.f;
-                ev[b][c][0] = ev[b][c][1] = ev[b][c][2] = 0.f;
-            }
-            if (idx[b] >= 0) {
-                float rec[REC];
-                load_record(g.data, idx[b], rec);
-                cv.sig[b] = rec[0];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float acc = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-                    for (int kk = 0; kk < 9; ++kk) {
-                        const float sh = rec[1 + 9 * c + kk];
-                        acc = fmaf(Y[kk], sh, acc);
-                        a0 = fmaf(GY[kk][0], sh, a0);
-                        a1 = fmaf(GY[kk][1], sh, a1);
-                        a2 = fmaf(GY[kk][2], sh, a2);
-                    }
-                    cv.e[b][c] = acc;
-                    ev[b][c][0] = a0; ev[b][c][1] = a1; ev[b][c][2] = a2;
-                }
-            }
-        }
-    } else {
-        load_corner_vals(g, idx, Y, cv);
-    }
-    float w[8];
-    trilinear_weights(s.f, w);
-    float sr = 0.f, sc[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        sr = fmaf(w[b], cv.sig[b], sr);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sc[c] = fmaf(w[b], cv.e[b][c], sc[c]);
-    }
+    Interp v;
+    gather_interp<true, VIEW>(g, idx, Y, GY, s.f, v);
+    const float sr = v.sig;
     if (!(sr > 0.f)) return;
     const float delta = op.step_vox;
     const float x = sr * delta;
@@ -397,49 +290,27 @@ __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op,
     float c[3], dact[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        c[ch] = act_fwd(op.act, sc[ch]);
-        dact[ch] = act_bwd(op.act, sc[ch]) * wt;
+        c[ch] = act_fwd(op.act, v.s[ch]);
+        dact[ch] = act_bwd(op.act, v.s[ch]) * wt;
         st.A[ch] = fmaf(wt, c[ch], st.A[ch]);
     }
     st.AD = fmaf(wt, s.t, st.AD);
     // per-output density factor (Eq. 9 / Eq. 10) and colour factor (Eq. 8)
-    float gsig[4], gsc[4];
+    float gsig[4];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        gsig[ch] = delta * (c[ch] * Tn - Chat[ch] + st.A[ch]);
-        gsc[ch] = dact[ch];
-    }
+    for (int ch = 0; ch < 3; ++ch) gsig[ch] = delta * (c[ch] * Tn - Chat[ch] + st.A[ch]);
     gsig[3] = delta * (s.t * Tn - Dhat + st.AD) / ray.s;
-    gsc[3] = 0.f;
-    const float fx = s.f[0], fy = s.f[1], fz = s.f[2];
-    const float gx0 = 1.f - fx, gy0 = 1.f - fy, gz0 = 1.f - fz;
     const float inv_vs = (float)g.inv_vs;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        float h[8];
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-            h[b] = gsig[k] * cv.sig[b] + (k < 3 ? gsc[k] * cv.e[b][k < 3 ? k : 0] : 0.f);
-        const float px = gy0 * gz0 * (h[4] - h[0]) + gy0 * fz * (h[5] - h[1])
-                       + fy * gz0 * (h[6] - h[2]) + fy * fz * (h[7] - h[3]);
-        const float py = gx0 * gz0 * (h[2] - h[0]) + gx0 * fz * (h[3] - h[1])
-                       + fx * gz0 * (h[6] - h[4]) + fx * fz * (h[7] - h[5]);
-        const float pz = gx0 * gy0 * (h[1] - h[0]) + gx0 * fy * (h[3] - h[2])
-                       + fx * gy0 * (h[5] - h[4]) + fx * fy * (h[7] - h[6]);
-        const float gp[3] = {px * inv_vs, py * inv_vs, pz * inv_vs};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ja.go[k][a] += gp[a];
-            ja.gd[k][a] = fmaf(s.t, gp[a], ja.gd[k][a]);
-        }
-        if (VIEW && k < 3) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                float acc = 0.f;
-#pragma unroll
-                for (int b = 0; b < 8; ++b) acc = fmaf(w[b], gsc[k] * ev[b][k < 3 ? k : 0][a], acc);
-                ja.gv[k][a] += acc;
-            }
+            float gp = gsig[k] * v.dsig[a];
+            if (k < 3) gp = fmaf(dact[k < 3 ? k : 0], v.ds[k < 3 ? k : 0][a], gp);
+            gp *= inv_vs;
+            ja.go[k][a] += gp;
+            ja.gd[k][a] = fmaf(s.t, gp, ja.gd[k][a]);
+            if (VIEW && k < 3) ja.gv[k][a] = fmaf(dact[k < 3 ? k : 0], v.ev[k < 3 ? k : 0][a], ja.gv[k][a]);
         }
     }
     st.T = Tn;
@@ -525,7 +396,7 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
                                                   float* __restrict__ grad,
                                                   double* __restrict__ grad_pose) {
     extern __shared__ float smem[];
-    WaveStage wc{nullptr, nullptr, nullptr};
+    WaveStage wc{nullptr, nullptr};
     if (GRID) wc = wave_stage(smem);
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = r < rs.n;
@@ -577,7 +448,7 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
                                                unsigned* __restrict__ ws, int persistent) {
     __shared__ int64_t s_tile;
     extern __shared__ float smem[];
-    WaveStage wc{nullptr, nullptr, nullptr};
+    WaveStage wc{nullptr, nullptr};
     if (GRID) wc = wave_stage(smem);
     const int64_t n_tiles = (rs.n + blockDim.x - 1) / blockDim.x;
     // Persistent form: workgroups take tiles in order from one queue counter

@@ -10,8 +10,9 @@
 //     G[l][0] = dL/d sigma_raw,  G[l][1 + 9c + k] = dL/ds_c * Y_k(d_l),
 // a small dense contraction over the 64 lanes.  Up to four groups (32 rows)
 // are contracted per pass on the matrix cores with 32 FP32 MFMA 32x32x2
-// instructions (K = 2 lanes each); W and G are staged in LDS in the operand
-// order the instruction reads.  The 32 x 28 totals go to HBM with atomics,
+// instructions (K = 2 lanes each).  G is staged in LDS in the operand order
+// the instruction reads; W is formed on the fly from the lanes' staged
+// trilinear weights and the groups' member masks.  The 32 x 28 totals go to HBM with atomics,
 // each instruction covering the two contiguous 112-byte records of corners r
 // and 4 + r of a group.  (A per-wave LDS write-combining cache in front of
 // the atomics saved HBM writes but its 7 KB per wave lowered occupancy from
@@ -25,23 +26,23 @@ namespace pxm {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
-// per-wave LDS: MFMA operand staging and the lanes' trilinear weights
+// per-wave LDS: the G operand and the lanes' trilinear weights
 // ---------------------------------------------------------------------------
 
 constexpr int STAGE_LD = 33;                              // padded row: conflict-free reads
-constexpr int STAGE_FLOATS = 64 * STAGE_LD;               // one operand: 64 rows (h*32 + i)
-constexpr int WAVE_LDS_FLOATS = 2 * STAGE_FLOATS + WAVE * 8;
+constexpr int STAGE_FLOATS = 64 * STAGE_LD;               // G: 64 rows (h*32 + i)
+constexpr int WAVE_LDS_FLOATS = STAGE_FLOATS + WAVE * 8;
 
 struct WaveStage {
-    float* sa;      // staged W operand
     float* sb;      // staged G operand
     float* sw;      // [WAVE][8] each lane's trilinear weights (16-byte aligned)
 };
 
 __device__ __forceinline__ WaveStage wave_stage(float* smem) {
     const int w = threadIdx.x / WAVE;
-    float* sa = smem + (size_t)w * WAVE_LDS_FLOATS;
-    return WaveStage{sa, sa + STAGE_FLOATS, sa + 2 * STAGE_FLOATS};
+    float* sb = smem + (size_t)w * WAVE_LDS_FLOATS;
+    float* sw = sb + STAGE_FLOATS;                        // 2112 floats in: 16-byte aligned
+    return WaveStage{sb, sw};
 }
 
 // Staging addresses.  Operand element for MFMA step c (lanes 2c and 2c+1) and
@@ -85,8 +86,8 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
 #pragma unroll
         for (int m = 0; m < REC; ++m) wc.sb[stage_at(m, lane)] = G[m];
         float4* sw = reinterpret_cast<float4*>(wc.sw + lane * 8);
-        sw[0] = make_float4(w[0], w[1], w[2], w[3]);
-        sw[1] = make_float4(w[4], w[5], w[6], w[7]);
+        sw[0] = have ? make_float4(w[0], w[1], w[2], w[3]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        sw[1] = have ? make_float4(w[4], w[5], w[6], w[7]) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -114,19 +115,20 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
         f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const int covered = __popcll(members[0] | members[1] | members[2] | members[3]);
         if (covered > SMALL_PASS_LANES) {
-            // W rows of this pass
-#pragma unroll
-            for (int g = 0; g < 4; ++g)
-#pragma unroll
-                for (int b = 0; b < 8; ++b) wc.sa[stage_at(g * 8 + b, lane)] = (grp == g) ? w[b] : 0.f;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // C = W^T G over the 64 lanes, two lanes per instruction
-            const float* pa = wc.sa + ((h << 5) + j) * STAGE_LD;
+            // C = W^T G over the 64 lanes, two lanes per instruction: step c
+            // takes rays 2c (h = 0) and 2c + 1 (h = 1); lane (h, j) supplies
+            // W[ray][row j] = w_{j%8}(ray) if the ray is in group j/8 (a bit of
+            // that group's member mask), and G[ray][j]
             const float* pb = wc.sb + ((h << 5) + j) * STAGE_LD;
+            const int jg = j >> 3, jb = j & 7;
+            const unsigned long long mine_mask =
+                jg == 0 ? members[0] : jg == 1 ? members[1] : jg == 2 ? members[2] : members[3];
+            const unsigned long long rows = mine_mask >> h;
 #pragma unroll
-            for (int c = 0; c < 32; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[c], pb[c], acc, 0, 0, 0);
+            for (int c = 0; c < 32; ++c) {
+                const float a = ((rows >> (2 * c)) & 1ull) ? wc.sw[(2 * c + h) * 8 + jb] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, pb[c], acc, 0, 0, 0);
+            }
         } else {
             // the same totals in the same register layout, member by member:
             // lane (h, j) adds w_{4h+r}(s) * G[s][j] into row 4h + r of group g
