@@ -331,7 +331,7 @@ def test_fused_c2_tiles_without_occupancy(c2):
 
 def test_fused_c2_full_frame(c2):
     """The whole 816,000-ray frame at the bench launch configuration."""
-    _fused_check(c2, 3, "c2 full")
+    _fused_check(c2, 3, "c2 full", block=64, variant=1)
 
 
 def test_tv_c2(c2):
