@@ -85,8 +85,9 @@ typedef struct {
     float aabb_min[3];      /* world position of vertex (0,0,0) */
     float voxel_size;       /* world edge length of one voxel, > 0 */
     const int32_t *link;    /* [Rx*Ry*Rz], index (x*Ry + y)*Rz + z -> record id or -1 */
-    int64_t n_alloc;        /* number of records */
-    const float *data;      /* [n_alloc][28], 16-byte aligned */
+    int64_t n_alloc;        /* number of records (0: an empty map, every link -1) */
+    const float *data;      /* [n_alloc][28], 16-byte aligned; may be NULL when n_alloc == 0,
+                               as may every grad_data argument */
     const uint32_t *occ;    /* optional occupancy bitfield from pxm_build_occupancy for THIS
                                link table, or NULL.  Lets the march step over empty cells and
                                8^3-cell bricks; results are identical with or without it. */

@@ -37,7 +37,8 @@ int check_grid(const pxm_grid* g, bool need_payload = true) {
     if (!g->link) return fail(PXM_INVALID_ARGUMENT, "grid.link is NULL");
     if (g->n_alloc < 0 || g->n_alloc > 2147483647LL)
         return fail(PXM_INVALID_ARGUMENT, "n_alloc = %lld outside [0, 2^31)", (long long)g->n_alloc);
-    if (need_payload && !g->data) return fail(PXM_INVALID_ARGUMENT, "grid.data is NULL");
+    if (need_payload && g->n_alloc > 0 && !g->data)
+        return fail(PXM_INVALID_ARGUMENT, "grid.data is NULL");
     if (g->data && (reinterpret_cast<uintptr_t>(g->data) & 15))
         return fail(PXM_INVALID_ARGUMENT, "grid.data must be 16-byte aligned");
     return PXM_OK;
@@ -176,8 +177,8 @@ int pxm_render_backward_grid(const pxm_grid* grid, const pxm_rays* rays, const p
     PXM_TRY(check_grid(grid));
     PXM_TRY(check_rays(rays));
     PXM_TRY(check_opts(opts));
-    if (!grad_data) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
-    if (rays->n_rays == 0) return PXM_OK;
+    if (!grad_data && grid->n_alloc > 0) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
+    if (rays->n_rays == 0 || grid->n_alloc == 0) return PXM_OK;   // no record can receive a gradient
     if (!rgb || !depth || !nsamp || !g_rgb || !g_depth)
         return fail(PXM_INVALID_ARGUMENT, "a required array is NULL");
     return launched(pxm::launch_backward(kgrid(grid), krays(rays), kopts(opts), rgb, depth, nsamp,
@@ -204,10 +205,11 @@ int pxm_render_backward_pose(const pxm_grid* grid, const pxm_rays* rays, const p
 int pxm_tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, float eps,
                 float* grad_data, void* stream) {
     PXM_TRY(check_grid(grid));
-    if (!grad_data) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
+    if (!grad_data && grid->n_alloc > 0) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
     if (!finite(lambda_density) || !finite(lambda_sh))
         return fail(PXM_INVALID_ARGUMENT, "lambda not finite");
     if (!(eps > 0.f) || !finite(eps)) return fail(PXM_INVALID_ARGUMENT, "eps must be finite and > 0");
+    if (grid->n_alloc == 0) return PXM_OK;                          // no vertex has a term
     if (reinterpret_cast<uintptr_t>(grad_data) & 15)
         return fail(PXM_INVALID_ARGUMENT, "grad_data must be 16-byte aligned");
     return launched(pxm::launch_tv(kgrid(grid), lambda_density, lambda_sh, eps, grad_data,
@@ -249,7 +251,8 @@ int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts*
         return fail(PXM_INVALID_ARGUMENT, "unknown want bits 0x%x", want);
     if (rays->n_rays > 0 && (!tgt_rgb || !tgt_depth || !frame_weight))
         return fail(PXM_INVALID_ARGUMENT, "targets / frame_weight is NULL");
-    if ((want & PXM_WANT_GRID) && !grad_data) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
+    if ((want & PXM_WANT_GRID) && !grad_data && grid->n_alloc > 0)
+        return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
     if ((want & PXM_WANT_POSE) && !grad_pose) return fail(PXM_INVALID_ARGUMENT, "grad_pose is NULL");
     if ((want & PXM_WANT_STATS) && !stats) return fail(PXM_INVALID_ARGUMENT, "stats is NULL");
     const size_t need = pxm_workspace_bytes(grid, rays, opts, want);

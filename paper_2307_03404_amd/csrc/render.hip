@@ -1,4 +1,5 @@
-// Forward, backward and fused kernels of the sparse-voxel volume renderer.
+// Forward, backward, fused and Gauss-Newton kernels of the sparse-voxel volume
+// renderer.
 //
 // One lane per ray.  A wave holds 64 rays of one pixel tile (the ray packer
 // orders full frames in 8x8 tiles), so the lanes gather nearly the same
@@ -8,7 +9,9 @@
 // cells (exact: they interpolate to zero density) and composite colour and
 // range.  Backward (Eq. 6-14): replay exactly the
 // forward's nsamp positions, re-deriving sigma, c, w and T_{i+1} (nothing is
-// stored per sample), and scatter or reduce the gradients.
+// stored per sample), and scatter or reduce the gradients.  Gauss-Newton
+// (Sec. 5.3): per-ray pose Jacobians of the four outputs from the same march,
+// reduced to per-frame normal equations.
 #include "internal.hpp"
 #include "scatter.hpp"
 

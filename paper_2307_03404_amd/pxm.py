@@ -185,7 +185,6 @@ class DeviceRays:
     intr: torch.Tensor           # float32 [F, 4]
     frame_offsets: torch.Tensor  # int32 [F+1]
     pix: torch.Tensor            # int32 [n_rays, 2]
-    offsets_host: np.ndarray = None
 
     @property
     def n_frames(self):
@@ -239,8 +238,7 @@ def rays_to_device(rays, device="cuda") -> DeviceRays:
     return DeviceRays(torch.from_numpy(np.ascontiguousarray(rays.c2w, np.float32)).to(device),
                       torch.from_numpy(np.ascontiguousarray(rays.intr, np.float32)).to(device),
                       torch.from_numpy(off).to(device),
-                      torch.from_numpy(np.ascontiguousarray(rays.pix, np.int32)).to(device),
-                      off.copy())
+                      torch.from_numpy(np.ascontiguousarray(rays.pix, np.int32)).to(device))
 
 
 # ----------------------------------------------------------------------------

@@ -6,7 +6,7 @@ import re
 
 import pytest
 
-from paper_2307_03404_amd import pxm
+from paper_2307_03404_amd import pxm, synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pxm.h")
@@ -169,3 +169,15 @@ def test_binding_rejects_host_tensors():
                           torch.zeros(1, 28))
     with pytest.raises(ValueError):
         grid.struct()
+
+
+def test_upload_helpers_build_descriptors():
+    """grid_to_device / rays_to_device assemble their dataclasses (on host
+    tensors here); handing them to the library is refused off the GPU."""
+    wl = synth.subset_rays(synth.config1(), 10)
+    g = pxm.grid_to_device(wl.grid, device="cpu", occupancy=False)
+    r = pxm.rays_to_device(wl.rays, device="cpu")
+    assert tuple(g.data.shape) == (wl.grid.n_alloc, 28) and g.link.numel() == 32 ** 3
+    assert r.n_rays == 10 and r.n_frames == 1 and r.frame_offsets.tolist() == [0, 10]
+    with pytest.raises(ValueError):
+        r.struct()

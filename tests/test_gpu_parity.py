@@ -381,6 +381,85 @@ def test_tv_ragged_bricks(reso):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_empty_grid_every_entry_point():
+    """A map with no allocated vertex (n_alloc = 0, data and gradients may be
+    NULL): transparent everywhere, zero gradients, a loss made of the targets
+    alone, TV and RMSProp no-ops, an all-empty occupancy bitfield."""
+    pxm = _dev()
+    wl = synth.subset_rays(synth.config1(), 500, seed=63)
+    R = wl.grid.reso
+    empty = synth.Grid(R, wl.grid.aabb_min, wl.grid.voxel_size,
+                       np.full(int(np.prod(R)), -1, np.int32), np.zeros((0, 28), np.float32))
+    wl = wl.replace(grid=empty)
+    ref = oracle.fused(empty, wl.rays, wl.targets, wl.opts)
+    g, r, t = to_dev(wl)
+    assert g.data.numel() == 0 and int(g.occ.sum()) == 0
+    n, F = wl.rays.n_rays, wl.rays.n_frames
+    rgb, depth, ns = pxm.render_forward(g, r, wl.opts)
+    loss = torch.zeros(F, dtype=torch.float64, device="cuda")
+    gd = torch.zeros_like(g.data)
+    gp = torch.zeros(F, 6, dtype=torch.float64, device="cuda")
+    pxm.render_fused(g, r, wl.opts, t["rgb"], t["depth"], t["fw"], 3, loss=loss, grad_data=gd,
+                     grad_pose=gp)
+    pxm.tv_grad(g, 0.1, 0.1, 1e-6, gd)
+    pxm.grid_rmsprop(g.data, gd, torch.zeros_like(g.data), 0.1, 0.1)
+    torch.cuda.synchronize()
+    assert np.all(np_(rgb) == 0) and np.all(np_(depth) == 0)
+    assert np.array_equal(np_(ns), ref["nsamp"])
+    assert_r28(np_(loss), ref["loss"], TAU_FWD, "empty-map loss")
+    assert np.all(np_(gp) == 0) and np.all(ref["grad_pose"] == 0)
+
+
+def test_axis_aligned_rays():
+    """Rays exactly parallel to lattice axes and lattice planes (direction
+    components exactly 0: the zero-step branches of the box entry and of the
+    brick jump), through a sparse grid with and without the occupancy
+    bitfield, against the oracle: forward, grid and pose gradients."""
+    pxm = _dev()
+    rng = np.random.default_rng(64)
+    grid = synth.random_tiny_grid(rng, R=40, margin=3, occupancy=0.15)
+    mats = []
+    for perm in ([0, 1, 2], [1, 2, 0], [2, 0, 1]):
+        Rm = np.eye(3)[:, perm]
+        if np.linalg.det(Rm) < 0:
+            Rm[:, 0] *= -1
+        c2w = np.zeros((3, 4))
+        c2w[:, :3] = Rm
+        c2w[:, 3] = -2.5 * Rm[:, 2] + 0.013 * rng.normal(size=3)
+        mats.append(c2w)
+    intr = np.array([[20.0, 20.0, 8.5, 8.5]] * 3)        # pixel (8, 8) looks along the optical axis
+    u, v = np.meshgrid(np.arange(17), np.arange(17))
+    pix = np.stack([u.ravel(), v.ravel()], 1).astype(np.int32)
+    keep = (pix[:, 0] == 8) | (pix[:, 1] == 8) | (rng.random(len(pix)) < 0.3)
+    pix = pix[keep]
+    rays = synth.Rays(np.asarray(mats, np.float32), intr.astype(np.float32),
+                      np.array([0, len(pix), 2 * len(pix), 3 * len(pix)], np.int32),
+                      np.concatenate([pix] * 3))
+    rgb0, depth0, _, _ = oracle.render(grid, rays, synth.Opts(step_vox=0.5, depth_loss=synth.DEPTH_L1))
+    tg = synth.Targets((rgb0 + 0.05).astype(np.float32), (depth0 * 1.02 + 0.01).astype(np.float32),
+                       synth.frame_weights(depth0 * 1.02 + 0.01, rays.frame_offsets, True))
+    wl = synth.Workload("axis", grid, rays, tg, synth.Opts(step_vox=0.5, depth_loss=synth.DEPTH_L2))
+    ref = oracle.fused(grid, rays, tg, wl.opts)
+    for occ in (True, False):
+        g = pxm.grid_to_device(grid, occupancy=occ)
+        r = pxm.rays_to_device(rays)
+        t = {k: torch.from_numpy(x).cuda() for k, x in
+             (("rgb", tg.rgb), ("depth", tg.depth), ("fw", tg.frame_weight))}
+        n, F = rays.n_rays, rays.n_frames
+        out_rgb = torch.empty(n, 3, device="cuda")
+        out_d = torch.empty(n, device="cuda")
+        gd = torch.zeros_like(g.data)
+        gp = torch.zeros(F, 6, dtype=torch.float64, device="cuda")
+        pxm.render_fused(g, r, wl.opts, t["rgb"], t["depth"], t["fw"], 3, rgb=out_rgb,
+                         depth=out_d, grad_data=gd, grad_pose=gp)
+        torch.cuda.synchronize()
+        what = f"axis-aligned (occupancy {occ})"
+        assert_r28(np_(out_rgb), ref["rgb"], TAU_FWD, what + " rgb")
+        assert_r28(np_(out_d), ref["depth"], TAU_FWD, what + " depth")
+        assert_r28(np_(gd), ref["grad_data"], TAU_GRAD, what + " grid")
+        assert_pose(np_(gp), ref["grad_pose"], TAU_GRAD, what + " pose")
+
+
 # ------------------------------------------------------------------ tracking update
 
 def test_pose_adam_matches_oracle(c3):
