@@ -20,7 +20,11 @@ namespace pxm {
 struct FwdResult {
     float C[3];
     float D;            // expected range (world units), Eq. 3
+    double Cd[3];       // the same sums in FP64, for the backward of the same kernel
+    double Dd;
     int n;              // kept sample positions
+    int mark_last;      // last word of the work-position mask written
+    bool mark_overflow; // a work position lay beyond the mask
     long long occ;      // samples in cells with an allocated corner
     long long occ_corners;
     long long grad_corners;   // allocated corners of samples with sigma_raw > 0
@@ -30,12 +34,27 @@ struct FwdResult {
 // in empty bricks are stepped over in one jump and empty cells cost one bit
 // test; both are exact (such samples interpolate to zero density) and still
 // count as kept positions.
+//
+// With a non-null `marks` the march also records, for the backward of the
+// same kernel, which of its positions passed the occupancy tests (the only
+// ones the backward has work at): bit o of the lane's mask is set for
+// position k_first + o, in words marks[w * WAVE] (w < MARK_WORDS) written
+// in order from a register; out.mark_last is the last word written and
+// out.mark_overflow is set if a marked position lay beyond the mask.
 __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, const Ray& ray,
-                                            const float Y[9], FwdResult& out) {
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, T = 1.f;
+                                            const float Y[9], FwdResult& out,
+                                            uint32_t* marks = nullptr) {
+    // colour and range are summed in FP64: the backward differences them
+    // with its own prefix sums (Eq. 9, 10), and in FP32 that difference
+    // would carry rounding that grows with the number of samples
+    double C0 = 0.0, C1 = 0.0, C2 = 0.0, D = 0.0;
+    float T = 1.f;
     double L = 0.0;
     int n = 0;
     long long occ = 0, occc = 0, gradc = 0;
+    int mw = 0;                     // current mark word
+    uint32_t mbits = 0;
+    bool movf = false;
     if (!ray.empty) {
         const float delta = op.step_vox;
         int64_t k = ray.k_first;
@@ -59,6 +78,20 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
                     continue;
                 }
             }
+            if (marks) {
+                const int64_t o = k - ray.k_first;
+                if (o >= (int64_t)MARK_WORDS * 32) {
+                    movf = true;
+                } else {
+                    const int w = (int)(o >> 5);
+                    while (mw < w) {
+                        marks[mw * WAVE] = mbits;
+                        mbits = 0u;
+                        ++mw;
+                    }
+                    mbits |= 1u << (int)(o & 31);
+                }
+            }
             ++n;
             ++k;
             int idx[8];
@@ -73,17 +106,22 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
             gradc += na;
             const float x = sr * delta;
             const float wt = T * (-expm1f(-x));
-            C0 = fmaf(wt, act_fwd(op.act, s0), C0);
-            C1 = fmaf(wt, act_fwd(op.act, s1), C1);
-            C2 = fmaf(wt, act_fwd(op.act, s2), C2);
-            D = fmaf(wt, s.t, D);
+            C0 = fma((double)wt, (double)act_fwd(op.act, s0), C0);
+            C1 = fma((double)wt, (double)act_fwd(op.act, s1), C1);
+            C2 = fma((double)wt, (double)act_fwd(op.act, s2), C2);
+            D = fma((double)wt, (double)s.t, D);
             L += (double)x;
             T = trans_of(L);
             if (T < op.t_stop) break;
         }
     }
-    out.C[0] = C0; out.C[1] = C1; out.C[2] = C2;
-    out.D = D;
+    if (marks) marks[mw * WAVE] = mbits;
+    out.mark_last = mw;
+    out.mark_overflow = movf;
+    out.Cd[0] = C0; out.Cd[1] = C1; out.Cd[2] = C2;
+    out.Dd = D;
+    out.C[0] = (float)C0; out.C[1] = (float)C1; out.C[2] = (float)C2;
+    out.D = (float)D;
     out.n = n;
     out.occ = occ;
     out.occ_corners = occc;
@@ -98,8 +136,8 @@ struct PoseAcc {
 
 // Running state of a backward march.
 struct BwdState {
-    float A[3];         // sum_{j<=i} c_j w_j
-    float AD;           // sum_{j<=i} t_j w_j
+    double A[3];        // sum_{j<=i} c_j w_j
+    double AD;          // sum_{j<=i} t_j w_j
     float T;            // T_i
     double L;           // sum_{j<i} sigma_j delta
 };
@@ -110,7 +148,7 @@ struct BwdState {
 template <bool POSE, bool VIEW>
 __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op, const Ray& ray,
                                                 const float Y[9], const float GY[9][3],
-                                                const Sample& s, const float Chat[3], float Dhat,
+                                                const Sample& s, const double Chat[3], double Dhat,
                                                 const float gC[3], float gDr, BwdState& st,
                                                 PoseAcc& pa, int idx[8], float w[8], float& gsig,
                                                 float gs[3]) {
@@ -130,14 +168,15 @@ __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op,
     for (int ch = 0; ch < 3; ++ch) {
         c[ch] = act_fwd(op.act, v.s[ch]);
         gs[ch] = act_bwd(op.act, v.s[ch]) * wt * gC[ch];      // Eq. 8 through act
-        st.A[ch] = fmaf(wt, c[ch], st.A[ch]);
+        st.A[ch] = fma((double)wt, (double)c[ch], st.A[ch]);
     }
-    st.AD = fmaf(wt, s.t, st.AD);
-    // Eq. 9 and Eq. 10 with inclusive prefixes A = sum_{j<=i} c_j w_j
-    gsig = delta * (gC[0] * (c[0] * Tn - Chat[0] + st.A[0])
-                  + gC[1] * (c[1] * Tn - Chat[1] + st.A[1])
-                  + gC[2] * (c[2] * Tn - Chat[2] + st.A[2])
-                  + gDr * (s.t * Tn - Dhat + st.AD));
+    st.AD = fma((double)wt, (double)s.t, st.AD);
+    // Eq. 9 and Eq. 10 with inclusive prefixes A = sum_{j<=i} c_j w_j; the
+    // suffix A - C-hat is formed in FP64
+    gsig = delta * (gC[0] * (c[0] * Tn + (float)(st.A[0] - Chat[0]))
+                  + gC[1] * (c[1] * Tn + (float)(st.A[1] - Chat[1]))
+                  + gC[2] * (c[2] * Tn + (float)(st.A[2] - Chat[2]))
+                  + gDr * (s.t * Tn + (float)(st.AD - Dhat)));
     if (POSE) {
         // Appendix A: the spatial gradient of the interpolant, dL/dp =
         // gsig grad(sigma) + sum_c gs_c grad(s_c), in world units
@@ -174,16 +213,47 @@ __device__ __forceinline__ int64_t wave_min(int64_t v) {
 // lane marches on its own.
 template <bool GRID, bool POSE, bool VIEW>
 __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, const Ray& ray,
-                                             const float Y[9], int n, const float Chat[3],
-                                             float Dhat, const float gC[3], float gDr,
+                                             const float Y[9], int n, const double Chat[3],
+                                             double Dhat, const float gC[3], float gDr,
                                              float* __restrict__ grad, const WaveStage& wc,
-                                             PoseAcc& pa) {
+                                             PoseAcc& pa, const uint32_t* marks = nullptr,
+                                             int mark_last = 0, bool mark_overflow = true) {
     float GY[9][3];
     if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
-    BwdState st = {{0.f, 0.f, 0.f}, 0.f, 1.f, 0.0};
+    BwdState st = {{0.0, 0.0, 0.0}, 0.0, 1.f, 0.0};
     const int64_t ks = ray.k_first, ke = ray.k_first + (n > 0 ? n : 0);
     bool has = n > 0;
-    if (GRID) {
+    if (GRID && marks && __ballot(mark_overflow && n > 0) == 0) {
+        // the forward of this kernel marked every work position: visit only
+        // those, the wave at the smallest pending one
+        auto next_mark = [&](int o) -> int {
+            int w = o >> 5;
+            if (w > mark_last) return -1;
+            uint32_t b = marks[w * WAVE] & (0xffffffffu << (o & 31));
+            while (b == 0u) {
+                if (++w > mark_last) return -1;
+                b = marks[w * WAVE];
+            }
+            return w * 32 + __ffs(b) - 1;
+        };
+        int off = has ? next_mark(0) : -1;
+        for (;;) {
+            const int64_t mine = off >= 0 ? ks + off : INT64_MAX;
+            const int64_t k = wave_min(mine);
+            if (k == INT64_MAX) break;
+            const bool work = mine == k;
+            bool have = false;
+            int idx[8];
+            float w[8];
+            float gsig = 0.f, gs[3] = {0.f, 0.f, 0.f};
+            Sample s;
+            if (work && sample_at(g, ray, k, s))
+                have = backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
+                                                   pa, idx, w, gsig, gs);
+            scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
+            if (work) off = next_mark(off + 1);
+        }
+    } else if (GRID) {
         int64_t k = wave_min(has ? ks : INT64_MAX);
         for (;;) {
             const bool live = has && k < ke;
@@ -277,7 +347,7 @@ struct JacAcc {
 template <bool VIEW>
 __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op, const Ray& ray,
                                                 const float Y[9], const float GY[9][3],
-                                                const Sample& s, const float Chat[3], float Dhat,
+                                                const Sample& s, const double Chat[3], double Dhat,
                                                 BwdState& st, JacAcc& ja) {
     int idx[8];
     if (load_links(g, s.base, idx) == 0) return;
@@ -295,14 +365,14 @@ __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op,
     for (int ch = 0; ch < 3; ++ch) {
         c[ch] = act_fwd(op.act, v.s[ch]);
         dact[ch] = act_bwd(op.act, v.s[ch]) * wt;
-        st.A[ch] = fmaf(wt, c[ch], st.A[ch]);
+        st.A[ch] = fma((double)wt, (double)c[ch], st.A[ch]);
     }
-    st.AD = fmaf(wt, s.t, st.AD);
+    st.AD = fma((double)wt, (double)s.t, st.AD);
     // per-output density factor (Eq. 9 / Eq. 10) and colour factor (Eq. 8)
     float gsig[4];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) gsig[ch] = delta * (c[ch] * Tn - Chat[ch] + st.A[ch]);
-    gsig[3] = delta * (s.t * Tn - Dhat + st.AD) / ray.s;
+    for (int ch = 0; ch < 3; ++ch) gsig[ch] = delta * (c[ch] * Tn + (float)(st.A[ch] - Chat[ch]));
+    gsig[3] = delta * (s.t * Tn + (float)(st.AD - Dhat)) / ray.s;
     const float inv_vs = (float)g.inv_vs;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -322,11 +392,11 @@ __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op,
 // Jacobian rows J[k] = (g_o, o x g_o + d x g_d (+ d x g_view)) of one ray.
 template <bool VIEW>
 __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, const Ray& ray,
-                                             const float Y[9], int n, const float Chat[3],
-                                             float Dhat, float J[4][6]) {
+                                             const float Y[9], int n, const double Chat[3],
+                                             double Dhat, float J[4][6]) {
     float GY[9][3];
     if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
-    BwdState st = {{0.f, 0.f, 0.f}, 0.f, 1.f, 0.0};
+    BwdState st = {{0.0, 0.0, 0.0}, 0.0, 1.f, 0.0};
     JacAcc ja;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -407,8 +477,10 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
     Ray ray;
     PoseAcc pa = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     float Y[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float gC[3] = {0.f, 0.f, 0.f}, Chat[3] = {0.f, 0.f, 0.f};
-    float gDr = 0.f, Dhat = 0.f;
+    float gC[3] = {0.f, 0.f, 0.f};
+    double Chat[3] = {0.0, 0.0, 0.0};
+    float gDr = 0.f;
+    double Dhat = 0.0;
     int n = 0;
     ray.empty = true;
     if (active) {
@@ -424,7 +496,7 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
             Chat[0] = rgb[3 * r];
             Chat[1] = rgb[3 * r + 1];
             Chat[2] = rgb[3 * r + 2];
-            Dhat = depth[r] * ray.s;
+            Dhat = (double)depth[r] * (double)ray.s;
             gDr = gD / ray.s;
             n = ray.empty ? 0 : nsamp[r];
         }
@@ -481,11 +553,14 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
         float gC[3] = {0.f, 0.f, 0.f};
         float gDr = 0.f;
         int nb = 0;
+        fr.mark_last = 0;
+        fr.mark_overflow = false;
+        uint32_t* marks = GRID ? wc.marks + lane_id() : nullptr;
         if (inr) {
             f = frame_of(rs.off, rs.F, r);
             setup_ray(g, rs, op, r, f, ray);
             sh9(ray.d[0], ray.d[1], ray.d[2], Y);
-            ray_forward(g, op, ray, Y, fr);
+            ray_forward(g, op, ray, Y, fr, marks);
             const float z = fr.D / ray.s;
             if (rgb_out) {
                 rgb_out[3 * r] = fr.C[0];
@@ -515,9 +590,11 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
             }
         } else {
             fr.C[0] = fr.C[1] = fr.C[2] = fr.D = 0.f;
+            fr.Cd[0] = fr.Cd[1] = fr.Cd[2] = fr.Dd = 0.0;
         }
         if (GRID || POSE)
-            ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, nb, fr.C, fr.D, gC, gDr, grad, wc, pa);
+            ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, nb, fr.Cd, fr.Dd, gC, gDr, grad, wc, pa, marks,
+                                           fr.mark_last, fr.mark_overflow);
         if (loss) {
             double lv[1] = {lval};
             seg_sum_atomic<1>(f, valid, lv, loss);
@@ -575,7 +652,7 @@ __global__ void __launch_bounds__(256) k_gn(KGrid g, KRays rs, KOpts op,
             const float e[4] = {fr.C[0] - tgt_rgb[3 * r], fr.C[1] - tgt_rgb[3 * r + 1],
                                 fr.C[2] - tgt_rgb[3 * r + 2], fr.D / ray.s - Dt};
             float J[4][6];
-            ray_jacobian<VIEW>(g, op, ray, Y, fr.n, fr.C, fr.D, J);
+            ray_jacobian<VIEW>(g, op, ray, Y, fr.n, fr.Cd, fr.Dd, J);
             const double wf = (double)fw[f];
             const double Wk[4] = {wf, wf, wf, wf * (double)op.lambda_d};
             int q = 0;

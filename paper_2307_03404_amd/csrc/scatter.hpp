@@ -26,23 +26,25 @@ namespace pxm {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
-// per-wave LDS: the G operand and the lanes' trilinear weights
+// per-wave LDS: the G operand, the lanes' trilinear weights and work masks
 // ---------------------------------------------------------------------------
 
 constexpr int STAGE_LD = 33;                              // padded row: conflict-free reads
 constexpr int STAGE_FLOATS = 64 * STAGE_LD;               // G: 64 rows (h*32 + i)
-constexpr int WAVE_LDS_FLOATS = STAGE_FLOATS + WAVE * 8;
+constexpr int MARK_WORDS = 32;                            // work-position mask: 1024 bits per lane
+constexpr int WAVE_LDS_FLOATS = STAGE_FLOATS + WAVE * 8 + MARK_WORDS * WAVE;
 
 struct WaveStage {
-    float* sb;      // staged G operand
-    float* sw;      // [WAVE][8] each lane's trilinear weights (16-byte aligned)
+    float* sb;          // staged G operand
+    float* sw;          // [WAVE][8] each lane's trilinear weights (16-byte aligned)
+    uint32_t* marks;    // [MARK_WORDS][WAVE] each lane's work-position mask (fused kernel)
 };
 
 __device__ __forceinline__ WaveStage wave_stage(float* smem) {
     const int w = threadIdx.x / WAVE;
     float* sb = smem + (size_t)w * WAVE_LDS_FLOATS;
     float* sw = sb + STAGE_FLOATS;                        // 2112 floats in: 16-byte aligned
-    return WaveStage{sb, sw};
+    return WaveStage{sb, sw, reinterpret_cast<uint32_t*>(sw + WAVE * 8)};
 }
 
 // Staging addresses.  Operand element for MFMA step c (lanes 2c and 2c+1) and

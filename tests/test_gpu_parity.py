@@ -460,6 +460,60 @@ def test_axis_aligned_rays():
         assert_pose(np_(gp), ref["grad_pose"], TAU_GRAD, what + " pose")
 
 
+def test_fused_long_rays_fall_back_to_scanning():
+    """Rays with more than 1024 work positions (a 600-voxel, nearly
+    transparent column) overflow the per-lane work mask the forward records,
+    and their wave's backward scans the grid instead; the other frame's
+    short rays, in another wave of the same launch, use the mask.  Both
+    against the oracle, with and without the occupancy bitfield."""
+    pxm = _dev()
+    rng = np.random.default_rng(66)
+    R = (6, 6, 600)
+    n = int(np.prod(R))
+    link = np.arange(n, dtype=np.int32)
+    data = np.zeros((n, 28), np.float32)
+    data[:, 0] = rng.uniform(0.001, 0.003, n)
+    data[:, 1:] = rng.normal(0, 0.3, (n, 27))
+    grid = synth.Grid(R, np.zeros(3, np.float32), synth.f32(0.01), link, data)
+    along = np.zeros((3, 4))
+    along[:, :3] = np.eye(3)
+    along[:, 3] = [0.025, 0.025, -0.3]                     # looking along +z down the column
+    across = np.zeros((3, 4))
+    across[:, :3] = np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], float).T
+    across[:, 3] = [0.3, 0.025, 3.0]                      # looking along -x across it
+    intr = np.array([[2000.0, 2000.0, 8.0, 8.0], [40.0, 40.0, 8.0, 8.0]], np.float32)
+    u, v = np.meshgrid(np.arange(4, 12), np.arange(4, 12))
+    pix = np.stack([u.ravel(), v.ravel()], 1).astype(np.int32)          # 64 rays per frame
+    rays = synth.Rays(np.stack([along, across]).astype(np.float32), intr,
+                      np.array([0, 64, 128], np.int32), np.concatenate([pix, pix]))
+    opts = synth.Opts(step_vox=0.5, depth_loss=synth.DEPTH_L2)
+    rgb0, depth0, nsamp, _ = oracle.render(grid, rays, opts)
+    assert nsamp[:64].max() > 1100 and nsamp[64:].max() < 1024
+    tg = synth.Targets((rgb0 + 0.05).astype(np.float32), (depth0 * 1.01).astype(np.float32),
+                       synth.frame_weights(depth0 * 1.01, rays.frame_offsets, True))
+    ref = oracle.fused(grid, rays, tg, opts)
+    for occ in (True, False):
+        g = pxm.grid_to_device(grid, occupancy=occ)
+        r = pxm.rays_to_device(rays)
+        t = [torch.from_numpy(x).cuda() for x in (tg.rgb, tg.depth, tg.frame_weight)]
+        out_rgb = torch.empty(128, 3, device="cuda")
+        out_d = torch.empty(128, device="cuda")
+        gd = torch.zeros_like(g.data)
+        gp = torch.zeros(2, 6, dtype=torch.float64, device="cuda")
+        old = pxm.get_tuning()
+        pxm.set_tuning(64, 1)
+        try:
+            pxm.render_fused(g, r, opts, *t, 3, rgb=out_rgb, depth=out_d, grad_data=gd, grad_pose=gp)
+            torch.cuda.synchronize()
+        finally:
+            pxm.set_tuning(*old)
+        what = f"long rays (occupancy {occ})"
+        assert_r28(np_(out_rgb), ref["rgb"], TAU_FWD, what + " rgb")
+        assert_r28(np_(out_d), ref["depth"], TAU_FWD, what + " depth")
+        assert_r28(np_(gd), ref["grad_data"], TAU_GRAD, what + " grid")
+        assert_pose(np_(gp), ref["grad_pose"], TAU_GRAD, what + " pose")
+
+
 # ------------------------------------------------------------------ tracking update
 
 def test_pose_adam_matches_oracle(c3):
