@@ -203,6 +203,19 @@ __device__ __forceinline__ int64_t wave_min(int64_t v) {
     return v;
 }
 
+// The smallest marked position offset >= o in a lane's work mask (words
+// marks[w * WAVE], w <= last), or -1.
+__device__ __forceinline__ int next_mark(const uint32_t* marks, int last, int o) {
+    int w = o >> 5;
+    if (w > last) return -1;
+    uint32_t b = marks[w * WAVE] & (0xffffffffu << (o & 31));
+    while (b == 0u) {
+        if (++w > last) return -1;
+        b = marks[w * WAVE];
+    }
+    return w * 32 + __ffs(b) - 1;
+}
+
 // Backward march of one ray over its first n kept positions (Eq. 6-14).
 //   Chat, Dhat: the forward's colour and expected range
 //   gC, gDr:    dL/dC-hat and dL/d(range)
@@ -226,17 +239,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
     if (GRID && marks && __ballot(mark_overflow && n > 0) == 0) {
         // the forward of this kernel marked every work position: visit only
         // those, the wave at the smallest pending one
-        auto next_mark = [&](int o) -> int {
-            int w = o >> 5;
-            if (w > mark_last) return -1;
-            uint32_t b = marks[w * WAVE] & (0xffffffffu << (o & 31));
-            while (b == 0u) {
-                if (++w > mark_last) return -1;
-                b = marks[w * WAVE];
-            }
-            return w * 32 + __ffs(b) - 1;
-        };
-        int off = has ? next_mark(0) : -1;
+        int off = has ? next_mark(marks, mark_last, 0) : -1;
         for (;;) {
             const int64_t mine = off >= 0 ? ks + off : INT64_MAX;
             const int64_t k = wave_min(mine);
@@ -251,7 +254,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
                 have = backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
                                                    pa, idx, w, gsig, gs);
             scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
-            if (work) off = next_mark(off + 1);
+            if (work) off = next_mark(marks, mark_last, off + 1);
         }
     } else if (GRID) {
         int64_t k = wave_min(has ? ks : INT64_MAX);
@@ -288,6 +291,18 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
                                                    pa, idx, w, gsig, gs);
             scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
             ++k;
+        }
+    } else if (marks && !mark_overflow) {
+        // per lane: straight from one marked position to the next
+        for (int off = has ? next_mark(marks, mark_last, 0) : -1; off >= 0;
+             off = next_mark(marks, mark_last, off + 1)) {
+            Sample s;
+            if (!sample_at(g, ray, ks + off, s)) break;
+            int idx[8];
+            float w[8];
+            float gsig, gs[3];
+            backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st, pa, idx, w,
+                                        gsig, gs);
         }
     } else {
         int64_t k = ks;
@@ -393,7 +408,9 @@ __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op,
 template <bool VIEW>
 __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, const Ray& ray,
                                              const float Y[9], int n, const double Chat[3],
-                                             double Dhat, float J[4][6]) {
+                                             double Dhat, float J[4][6],
+                                             const uint32_t* marks = nullptr, int mark_last = 0,
+                                             bool mark_overflow = true) {
     float GY[9][3];
     if (VIEW) sh9_grad(ray.d[0], ray.d[1], ray.d[2], GY);
     BwdState st = {{0.0, 0.0, 0.0}, 0.0, 1.f, 0.0};
@@ -403,23 +420,32 @@ __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, co
 #pragma unroll
         for (int a = 0; a < 3; ++a) ja.go[k][a] = ja.gd[k][a] = ja.gv[k][a] = 0.f;
     const int64_t ke = ray.k_first + (n > 0 ? n : 0);
-    int64_t k = ray.k_first;
-    while (k < ke) {
-        Sample s;
-        if (!sample_at(g, ray, k, s)) break;
-        if (g.occ0) {
-            if (brick_empty(g, s.c)) {
-                const int64_t nxt = brick_exit(g, ray, k, s.c);
-                k = nxt < ke ? nxt : ke;
-                continue;
-            }
-            if (!cell_occupied(g, s.c)) {
-                ++k;
-                continue;
-            }
+    if (marks && !mark_overflow) {
+        for (int off = n > 0 ? next_mark(marks, mark_last, 0) : -1; off >= 0;
+             off = next_mark(marks, mark_last, off + 1)) {
+            Sample s;
+            if (!sample_at(g, ray, ray.k_first + off, s)) break;
+            jacobian_sample<VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
         }
-        jacobian_sample<VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
-        ++k;
+    } else {
+        int64_t k = ray.k_first;
+        while (k < ke) {
+            Sample s;
+            if (!sample_at(g, ray, k, s)) break;
+            if (g.occ0) {
+                if (brick_empty(g, s.c)) {
+                    const int64_t nxt = brick_exit(g, ray, k, s.c);
+                    k = nxt < ke ? nxt : ke;
+                    continue;
+                }
+                if (!cell_occupied(g, s.c)) {
+                    ++k;
+                    continue;
+                }
+            }
+            jacobian_sample<VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
+            ++k;
+        }
     }
     const float* o = ray.o;
     const float* d = ray.d;
@@ -555,7 +581,10 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
         int nb = 0;
         fr.mark_last = 0;
         fr.mark_overflow = false;
-        uint32_t* marks = GRID ? wc.marks + lane_id() : nullptr;
+        uint32_t* marks = GRID ? wc.marks + lane_id()
+                        : POSE ? reinterpret_cast<uint32_t*>(smem) + (threadIdx.x / WAVE) * (MARK_WORDS * WAVE)
+                                     + lane_id()
+                               : nullptr;
         if (inr) {
             f = frame_of(rs.off, rs.F, r);
             setup_ray(g, rs, op, r, f, ray);
@@ -631,6 +660,8 @@ __global__ void __launch_bounds__(256) k_gn(KGrid g, KRays rs, KOpts op,
                                             const float* __restrict__ tgt_depth,
                                             const float* __restrict__ fw,
                                             double* __restrict__ gn) {
+    extern __shared__ uint32_t gn_marks[];
+    uint32_t* marks = gn_marks + (threadIdx.x / WAVE) * (MARK_WORDS * WAVE) + lane_id();
     const int64_t r = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool inr = r < rs.n;
     int f = 0;
@@ -645,14 +676,15 @@ __global__ void __launch_bounds__(256) k_gn(KGrid g, KRays rs, KOpts op,
         float Y[9];
         sh9(ray.d[0], ray.d[1], ray.d[2], Y);
         FwdResult fr;
-        ray_forward(g, op, ray, Y, fr);
+        ray_forward(g, op, ray, Y, fr, marks);
         const float Dt = tgt_depth[r];
         valid = isfinite(Dt) && Dt > 0.f;
         if (valid) {
             const float e[4] = {fr.C[0] - tgt_rgb[3 * r], fr.C[1] - tgt_rgb[3 * r + 1],
                                 fr.C[2] - tgt_rgb[3 * r + 2], fr.D / ray.s - Dt};
             float J[4][6];
-            ray_jacobian<VIEW>(g, op, ray, Y, fr.n, fr.Cd, fr.Dd, J);
+            ray_jacobian<VIEW>(g, op, ray, Y, fr.n, fr.Cd, fr.Dd, J, marks, fr.mark_last,
+                               fr.mark_overflow);
             const double wf = (double)fw[f];
             const double Wk[4] = {wf, wf, wf, wf * (double)op.lambda_d};
             int q = 0;
@@ -760,7 +792,8 @@ static void fused_go(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, 
                      const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                      const float* fw, float* rgb, float* depth, double* loss, float* grad,
                      double* gp, int64_t* stats, unsigned* ws, int persistent) {
-    const size_t lds = GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float) : 0;
+    const size_t lds = GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float)
+                     : POSE ? (block.x / WAVE) * MARK_WORDS * WAVE * sizeof(uint32_t) : 0;
     const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW>(block.x, lds, tiles)
                                : (unsigned)tiles);
     hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW>), grid, block, lds, st, g, rs, op, tgt_rgb,
@@ -801,11 +834,12 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
 hipError_t launch_gn(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,
                      const float* tgt_depth, const float* frame_weight, double* gn, hipStream_t st) {
     const dim3 grid(blocks_for(rs.n, 256)), block(256);
+    const size_t lds = (256 / WAVE) * MARK_WORDS * WAVE * sizeof(uint32_t);
     if (op.flags & 1)
-        hipLaunchKernelGGL((k_gn<true>), grid, block, 0, st, g, rs, op, tgt_rgb, tgt_depth,
+        hipLaunchKernelGGL((k_gn<true>), grid, block, lds, st, g, rs, op, tgt_rgb, tgt_depth,
                            frame_weight, gn);
     else
-        hipLaunchKernelGGL((k_gn<false>), grid, block, 0, st, g, rs, op, tgt_rgb, tgt_depth,
+        hipLaunchKernelGGL((k_gn<false>), grid, block, lds, st, g, rs, op, tgt_rgb, tgt_depth,
                            frame_weight, gn);
     return hipGetLastError();
 }

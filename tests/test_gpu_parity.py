@@ -512,6 +512,16 @@ def test_fused_long_rays_fall_back_to_scanning():
         assert_r28(np_(out_d), ref["depth"], TAU_FWD, what + " depth")
         assert_r28(np_(gd), ref["grad_data"], TAU_GRAD, what + " grid")
         assert_pose(np_(gp), ref["grad_pose"], TAU_GRAD, what + " pose")
+        # the per-lane marches (pose only, Gauss-Newton) fall back lane by lane
+        gp.zero_()
+        pxm.render_fused(g, r, opts, *t, 2, grad_pose=gp)
+        H, gv, E = oracle.gn_system(grid, rays, tg, opts)
+        gn = pxm.render_gn(g, r, opts, *t)
+        torch.cuda.synchronize()
+        assert_pose(np_(gp), ref["grad_pose"], TAU_GRAD, what + " pose-only launch")
+        Hg, gg, Eg = (np_(x) for x in pxm.gn_unpack(gn))
+        assert_r28(Hg, H, TAU_GRAD, what + " Gauss-Newton H")
+        assert_r28(gg, gv, TAU_GRAD, what + " Gauss-Newton g")
 
 
 # ------------------------------------------------------------------ tracking update
