@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define PXM_ABI_VERSION 2
+#define PXM_ABI_VERSION 3   /* 3: optimiser and Gauss-Newton entry points, empty maps */
 #define PXM_RECORD 28          /* floats per vertex: density + 3 x 9 SH */
 
 typedef enum {

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(pxm.EXPORTS) == set(names)
-    assert pxm.abi_version() == 2
+    assert pxm.abi_version() == 3
 
 
 def test_status_strings():
