@@ -5,12 +5,14 @@ leg of the benchmark may import this package; the product path never does.
 It shares no code with the HIP kernels.  Its C core (``oracle.c``) follows the
 paper's equations one ray at a time in double precision; this module only
 marshals numpy arrays, plus small textbook pieces in numpy (the SE(3)
-exponential map, an Adam step for tracking and a sparse RMSProp step for
-mapping).
+exponential map, an Adam step for tracking, a sparse RMSProp step for
+mapping, and the dynamic-grid edits: coarse-to-fine growth and pruning).
 
 Parity unpinned by the paper: the colour activation, the SH sign/order
 convention, the se(3) pose parametrisation, the default (position-only)
-pose chain, early termination and the TV regulariser are readings; they are
+pose chain, early termination, the TV regulariser and the growth/pruning
+rules of the dynamic grid (the paper names a dynamic grid with a 512^3 peak
+and gives no policy) are readings; they are
 pinned by finite differences, closed forms and invariants, not by numbers
 the paper prints (it prints none for this path).
 """
@@ -351,3 +353,76 @@ def rmsprop_grid(data, grad, state, lr_density, lr_sh, alpha, eps):
     state[touched] = v
     data[touched] = data[touched] - lr[None, :] * gt / (np.sqrt(v) + eps)
     return data, state
+
+
+def grid_upsample(grid):
+    """Coarse-to-fine growth of the map: the lattice of R vertices per axis
+    becomes 2R - 1, fine vertex 2v sitting on coarse vertex v (voxel size
+    halved, same origin).  A fine vertex is allocated when it lies in (the
+    closure of) a coarse cell with an allocated corner, in lattice order;
+    its record is the coarse trilinear interpolant at its position (empty
+    corners read 0), with the density halved: density is per voxel, so the
+    optical depth of a world-length step is unchanged.  Returns a new grid
+    (float32 records rounded from FP64)."""
+    import dataclasses
+    R = np.asarray(grid.reso, np.int64)
+    link = np.asarray(grid.link, np.int64).reshape(tuple(R))
+    data = np.asarray(grid.data, np.float64)
+    alloc = link >= 0
+    occ = np.zeros(tuple(R - 1), bool)                      # cell has an allocated corner
+    for dx in (0, 1):
+        for dy in (0, 1):
+            for dz in (0, 1):
+                occ |= alloc[dx:R[0] - 1 + dx, dy:R[1] - 1 + dy, dz:R[2] - 1 + dz]
+    Rf = 2 * R - 1
+
+    def cells(axis_n, Rc):
+        # coarse cells containing each fine coordinate: even -> v-1, v; odd -> (v-1)/2
+        lo = np.where(axis_n % 2 == 0, axis_n // 2 - 1, (axis_n - 1) // 2)
+        hi = np.where(axis_n % 2 == 0, axis_n // 2, (axis_n - 1) // 2)
+        return np.clip(lo, 0, Rc - 2), np.clip(hi, 0, Rc - 2)
+
+    X, Y, Z = (np.arange(n) for n in Rf)
+    xl, xh = cells(X, R[0])
+    yl, yh = cells(Y, R[1])
+    zl, zh = cells(Z, R[2])
+    mask = np.zeros(tuple(Rf), bool)
+    for xs in (xl, xh):
+        for ys in (yl, yh):
+            for zs in (zl, zh):
+                mask |= occ[xs[:, None, None], ys[None, :, None], zs[None, None, :]]
+    flat = mask.ravel()
+    new_link = np.full(flat.size, -1, np.int32)
+    idx = np.flatnonzero(flat)
+    new_link[idx] = np.arange(idx.size, dtype=np.int32)
+    # fine vertex positions in coarse voxel units, and their interpolated records
+    fx, fy, fz = np.unravel_index(idx, tuple(Rf))
+    q = np.stack([fx, fy, fz], 1) / 2.0
+    c = np.minimum(np.floor(q).astype(np.int64), R - 2)
+    f = q - c
+    vals = np.zeros((idx.size, NREC))
+    for b in range(8):
+        o = np.array([(b >> 2) & 1, (b >> 1) & 1, b & 1])
+        w = np.prod(np.where(o[None, :] == 1, f, 1.0 - f), axis=1)
+        v = c + o[None, :]
+        lid = link[v[:, 0], v[:, 1], v[:, 2]]
+        ok = lid >= 0
+        vals[ok] += w[ok, None] * data[lid[ok]]
+    vals[:, 0] *= 0.5
+    return dataclasses.replace(grid, reso=tuple(int(r) for r in Rf),
+                               voxel_size=np.float32(grid.voxel_size / 2), link=new_link,
+                               data=vals.astype(np.float32))
+
+
+def grid_prune(grid, tau):
+    """Prune the map: records whose density is <= tau are dropped, the others
+    keep their order and are renumbered, and the link table is rewritten
+    (a dropped vertex becomes empty).  Returns a new grid."""
+    import dataclasses
+    data = np.asarray(grid.data)
+    keep = data[:, 0] > np.float32(tau)
+    new_id = np.full(data.shape[0], -1, np.int64)
+    new_id[keep] = np.arange(int(keep.sum()))
+    link = np.asarray(grid.link, np.int64)
+    new_link = np.where(link >= 0, new_id[np.maximum(link, 0)], -1).astype(np.int32)
+    return dataclasses.replace(grid, link=new_link, data=data[keep].copy())

@@ -614,3 +614,120 @@ def test_gn_steps_recover_the_pose():
     assert all(b < a for a, b in zip(errs[:5], errs[1:6]))
     assert errs[-1] < 1e-12 * errs[0]
     np.testing.assert_allclose(c2w, true, atol=1e-6)
+
+
+# ------------------------------------------- dynamic grid (Sec. 5, peak 512^3)
+
+def _fine_bruteforce(g):
+    """Allocation mask and records of the doubled lattice by brute force:
+    a fine vertex is allocated when some coarse cell whose closed box holds
+    it has an allocated corner; its record is the separable midpoint average
+    of the coarse records along each odd axis (empty corners read 0)."""
+    R = g.reso[0]
+    link = g.link.reshape(R, R, R)
+    Rf = 2 * R - 1
+    mask = np.zeros((Rf, Rf, Rf), bool)
+    vals = np.zeros((Rf, Rf, Rf, oracle.NREC))
+
+    def rec(x, y, z):
+        i = link[x, y, z]
+        return np.zeros(oracle.NREC) if i < 0 else g.data[i].astype(np.float64)
+
+    for fx in range(Rf):
+        for fy in range(Rf):
+            for fz in range(Rf):
+                p = np.array([fx, fy, fz]) / 2.0
+                for cx in range(R - 1):
+                    for cy in range(R - 1):
+                        for cz in range(R - 1):
+                            c = np.array([cx, cy, cz])
+                            if np.all(p >= c) and np.all(p <= c + 1) and \
+                                    (link[cx:cx + 2, cy:cy + 2, cz:cz + 2] >= 0).any():
+                                mask[fx, fy, fz] = True
+                # midpoint averages: axis coordinate 2a -> a, 2a+1 -> {a, a+1}
+                sets = [[f // 2] if f % 2 == 0 else [f // 2, f // 2 + 1] for f in (fx, fy, fz)]
+                acc = np.zeros(oracle.NREC)
+                for x in sets[0]:
+                    for y in sets[1]:
+                        for z in sets[2]:
+                            acc += rec(x, y, z)
+                vals[fx, fy, fz] = acc / (len(sets[0]) * len(sets[1]) * len(sets[2]))
+    vals[..., 0] *= 0.5
+    return mask.ravel(), vals.reshape(-1, oracle.NREC)
+
+
+def test_upsample_matches_bruteforce_allocation_and_midpoint_records():
+    rng = np.random.default_rng(61)
+    g = synth.random_tiny_grid(rng, R=5, margin=1, occupancy=0.4)
+    g.link[0] = g.data.shape[0] - 1          # a corner vertex too (clipped cells)
+    fine = oracle.grid_upsample(g)
+    assert fine.reso == (9, 9, 9) and fine.voxel_size == np.float32(g.voxel_size / 2)
+    np.testing.assert_array_equal(fine.aabb_min, g.aabb_min)
+    mask, vals = _fine_bruteforce(g)
+    np.testing.assert_array_equal(fine.link >= 0, mask)
+    idx = np.flatnonzero(mask)
+    np.testing.assert_array_equal(fine.link[idx], np.arange(idx.size))   # lattice order
+    np.testing.assert_allclose(fine.data, vals[idx], rtol=1e-7, atol=1e-7)
+
+
+def test_upsample_keeps_the_interpolated_field():
+    """Trilinear fields restrict exactly to the eight sub-cells of a cell, so
+    the fine map interpolates to the coarse field (density halved: it is per
+    voxel) at every point, not only at vertices."""
+    rng = np.random.default_rng(62)
+    g = synth.random_tiny_grid(rng, R=7, margin=1, occupancy=0.5)
+    fine = oracle.grid_upsample(g)
+    scale = np.abs(g.data).max()
+    for q in rng.uniform(0.0, 6.0, size=(60, 3)):
+        vc, _ = oracle.interp(g, q, want_grad=False)
+        vf, _ = oracle.interp(fine, 2.0 * q, want_grad=False)
+        vf[0] *= 2.0
+        np.testing.assert_allclose(vf, vc, rtol=0, atol=2e-7 * scale)
+
+
+@pytest.mark.parametrize("act", [synth.COLOR_SIGMOID, synth.COLOR_IDENTITY])
+def test_upsample_render_at_half_step_is_unchanged(act):
+    """Rendering the doubled map with twice the step in voxel units samples the
+    same world points with the same optical depth per sample (Eq. 1-3)."""
+    g, rays, opts, _, _ = _tiny_workload(63 + act, act=act, occupancy=0.6)
+    fine = oracle.grid_upsample(g)
+    rgb_c, dep_c, n_c, _ = oracle.render(g, rays, opts)
+    rgb_f, dep_f, _, _ = oracle.render(fine, rays, dataclasses.replace(opts, step_vox=2 * opts.step_vox))
+    assert (n_c > 0).sum() > 10
+    np.testing.assert_allclose(rgb_f, rgb_c, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(dep_f, dep_c, rtol=0, atol=2e-6)
+
+
+def test_prune_drops_low_density_records_in_order():
+    rng = np.random.default_rng(64)
+    g = synth.random_tiny_grid(rng, R=7, margin=1, occupancy=0.7)
+    tau = np.float32(np.median(g.data[:, 0]))
+    p = oracle.grid_prune(g, tau)
+    keep = g.data[:, 0] > tau
+    assert p.n_alloc == int(keep.sum()) and 0 < p.n_alloc < g.n_alloc
+    for v in range(g.link.size):
+        old = g.link[v]
+        if old < 0 or not keep[old]:
+            assert p.link[v] == -1
+        else:
+            assert np.array_equal(p.data[p.link[v]], g.data[old])
+    live = p.link[p.link >= 0]
+    assert np.array_equal(np.sort(live), np.arange(p.n_alloc))
+    assert np.all(np.diff(live) > 0)                        # order kept
+    same = oracle.grid_prune(g, np.float32(g.data[:, 0].min()) - 1)
+    assert np.array_equal(same.link, g.link) and np.array_equal(same.data, g.data)
+
+
+def test_prune_of_zero_records_leaves_renders_unchanged():
+    """An all-zero record reads the same as an empty vertex."""
+    g, rays, opts, _, _ = _tiny_workload(65, occupancy=0.9)
+    rng = np.random.default_rng(66)
+    zero = rng.random(g.n_alloc) < 0.3
+    g.data[zero] = 0.0
+    g.data[~zero, 0] = np.abs(g.data[~zero, 0]) + 0.01
+    p = oracle.grid_prune(g, 0.0)
+    assert p.n_alloc == int((~zero).sum())
+    rgb0, dep0, _, _ = oracle.render(g, rays, opts)
+    rgb1, dep1, _, _ = oracle.render(p, rays, opts)
+    np.testing.assert_allclose(rgb1, rgb0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(dep1, dep0, rtol=0, atol=1e-13)
