@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define PXM_ABI_VERSION 3   /* 3: optimiser and Gauss-Newton entry points, empty maps */
+#define PXM_ABI_VERSION 4   /* 4: dynamic-grid growth and pruning */
 #define PXM_RECORD 28          /* floats per vertex: density + 3 x 9 SH */
 
 typedef enum {
@@ -263,6 +263,62 @@ int pxm_grid_rmsprop(int64_t n_alloc, float *data, float *grad_data, float *stat
  */
 size_t pxm_occupancy_words(const pxm_grid *grid);
 int pxm_build_occupancy(const pxm_grid *grid, uint32_t *occ, size_t n_words, void *stream);
+
+/*
+ * Dynamic grid (Sec. 5: a dynamic voxel grid with a peak resolution of
+ * 512^3; the paper gives no growth or pruning policy, so the schedule is the
+ * caller's).  Both edits write a new link table and a new payload; the
+ * caller then rebuilds the occupancy bitfield of the new grid.
+ *
+ * Workspace.  `ws` is device scratch of at least
+ * pxm_grid_edit_workspace_bytes(grid) bytes, 256-byte aligned.  Its contents
+ * on entry do not matter and are left undefined: a buffer shared with
+ * pxm_render_fused must be zeroed again before that call.
+ *
+ * Counts.  n_fine / n_out are DEVICE int64 written on `stream`; synchronise
+ * before reading them.
+ */
+size_t pxm_grid_edit_workspace_bytes(const pxm_grid *grid);
+
+/*
+ * Coarse-to-fine growth, step 1 of 2: the link table of the doubled lattice.
+ * The fine grid has 2R - 1 vertices per axis, voxel_size / 2 and the same
+ * aabb_min, so fine vertex 2v sits on coarse vertex v.  A fine vertex is
+ * allocated when some coarse cell whose closed box holds it has an allocated
+ * corner; allocated fine vertices are numbered 0 .. n_fine-1 in lattice order.
+ *   link_fine  [(2Rx-1)(2Ry-1)(2Rz-1)] int32, written (-1 = empty)
+ *   n_fine     device int64, written
+ * grid->data is not read.  PXM_UNSUPPORTED when the doubled lattice exceeds
+ * 2^31 - 1 vertices.
+ */
+int pxm_grid_upsample_link(const pxm_grid *grid, int32_t *link_fine, int64_t *n_fine, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/*
+ * Coarse-to-fine growth, step 2 of 2: the fine records.  Each is the coarse
+ * trilinear interpolant at the fine vertex (empty coarse vertices read 0),
+ * summed in FP64 and rounded once to FP32, with the density halved: density
+ * is per voxel, so the optical depth of a world-length step is unchanged and
+ * rendering the fine grid at twice the step_vox reproduces the coarse render.
+ *   link_fine  the table step 1 wrote for this grid
+ *   n_fine     its count (host value, read back by the caller)
+ *   data_fine  [n_fine][28] f32, 16-byte aligned, written
+ */
+int pxm_grid_upsample_data(const pxm_grid *grid, const int32_t *link_fine, int64_t n_fine,
+                           float *data_fine, void *stream);
+
+/*
+ * Pruning: records whose density is <= tau are dropped; the others keep their
+ * order and are renumbered 0 .. n_out-1, and the link table is rewritten
+ * (dropped or invalid links -> -1).
+ *   link_out  [Rx*Ry*Rz] int32, written; may be grid->link itself (in place)
+ *   data_out  [n_alloc][28] f32 capacity, 16-byte aligned, must not overlap
+ *             grid->data; rows [0, n_out) are written
+ *   n_out     device int64, written
+ * tau = -inf keeps every record.  NaN tau is PXM_INVALID_ARGUMENT.
+ */
+int pxm_grid_prune(const pxm_grid *grid, float tau, int32_t *link_out, float *data_out,
+                   int64_t *n_out, void *ws, size_t ws_bytes, void *stream);
 
 /* Workspace bytes pxm_render_fused needs for these arguments and `want`. */
 size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,

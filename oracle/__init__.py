@@ -424,5 +424,7 @@ def grid_prune(grid, tau):
     new_id = np.full(data.shape[0], -1, np.int64)
     new_id[keep] = np.arange(int(keep.sum()))
     link = np.asarray(grid.link, np.int64)
-    new_link = np.where(link >= 0, new_id[np.maximum(link, 0)], -1).astype(np.int32)
+    new_link = np.full(link.shape, -1, np.int32)
+    live = link >= 0
+    new_link[live] = new_id[link[live]]
     return dataclasses.replace(grid, link=new_link, data=data[keep].copy())

@@ -315,4 +315,83 @@ int pxm_grid_rmsprop(int64_t n_alloc, float* data, float* grad_data, float* stat
                                         eps, (hipStream_t)stream), "grid_rmsprop");
 }
 
+size_t pxm_grid_edit_workspace_bytes(const pxm_grid* grid) {
+    if (check_grid(grid, false) != PXM_OK) return 0;
+    const int64_t nf = (int64_t)(2 * grid->reso[0] - 1) * (2 * grid->reso[1] - 1) * (2 * grid->reso[2] - 1);
+    const size_t up = pxm::compaction_bytes(nf);
+    const size_t pr = pxm::compaction_bytes(grid->n_alloc) + 4 * (size_t)grid->n_alloc;
+    return up > pr ? up : pr;
+}
+
+namespace {
+
+int check_edit_ws(const pxm_grid* grid, void* ws, size_t ws_bytes) {
+    const size_t need = pxm_grid_edit_workspace_bytes(grid);
+    if (ws_bytes < need) return fail(PXM_WORKSPACE_TOO_SMALL, "ws_bytes = %zu < %zu", ws_bytes, need);
+    if (!ws) return fail(PXM_INVALID_ARGUMENT, "ws is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(PXM_INVALID_ARGUMENT, "ws must be 256-byte aligned");
+    return PXM_OK;
+}
+
+int64_t fine_vertices(const pxm_grid* grid) {
+    return (int64_t)(2 * grid->reso[0] - 1) * (2 * grid->reso[1] - 1) * (2 * grid->reso[2] - 1);
+}
+
+}  // namespace
+
+int pxm_grid_upsample_link(const pxm_grid* grid, int32_t* link_fine, int64_t* n_fine, void* ws, size_t ws_bytes,
+                           void* stream) {
+    PXM_TRY(check_grid(grid, false));
+    for (int a = 0; a < 3; ++a)
+        if (grid->reso[a] > 1073741823) return fail(PXM_UNSUPPORTED, "reso[%d] too large to double", a);
+    if (fine_vertices(grid) > 2147483647LL)
+        return fail(PXM_UNSUPPORTED, "doubled lattice has more than 2^31 - 1 vertices");
+    if (!link_fine || !n_fine) return fail(PXM_INVALID_ARGUMENT, "link_fine / n_fine is NULL");
+    PXM_TRY(check_edit_ws(grid, ws, ws_bytes));
+    return launched(pxm::launch_upsample_link(kgrid(grid), link_fine, n_fine, ws, (hipStream_t)stream),
+                    "grid_upsample_link");
+}
+
+int pxm_grid_upsample_data(const pxm_grid* grid, const int32_t* link_fine, int64_t n_fine, float* data_fine,
+                           void* stream) {
+    PXM_TRY(check_grid(grid, true));
+    for (int a = 0; a < 3; ++a)
+        if (grid->reso[a] > 1073741823) return fail(PXM_UNSUPPORTED, "reso[%d] too large to double", a);
+    if (fine_vertices(grid) > 2147483647LL)
+        return fail(PXM_UNSUPPORTED, "doubled lattice has more than 2^31 - 1 vertices");
+    if (!link_fine) return fail(PXM_INVALID_ARGUMENT, "link_fine is NULL");
+    if (n_fine < 0 || n_fine > fine_vertices(grid))
+        return fail(PXM_INVALID_ARGUMENT, "n_fine = %lld outside [0, fine vertices]", (long long)n_fine);
+    if (n_fine == 0) return PXM_OK;
+    if (!data_fine) return fail(PXM_INVALID_ARGUMENT, "data_fine is NULL");
+    if (reinterpret_cast<uintptr_t>(data_fine) & 15)
+        return fail(PXM_INVALID_ARGUMENT, "data_fine must be 16-byte aligned");
+    return launched(pxm::launch_upsample_data(kgrid(grid), link_fine, n_fine, data_fine, (hipStream_t)stream),
+                    "grid_upsample_data");
+}
+
+int pxm_grid_prune(const pxm_grid* grid, float tau, int32_t* link_out, float* data_out, int64_t* n_out, void* ws,
+                   size_t ws_bytes, void* stream) {
+    PXM_TRY(check_grid(grid, true));
+    if (std::isnan(tau)) return fail(PXM_INVALID_ARGUMENT, "tau is NaN");
+    if (!link_out || !n_out) return fail(PXM_INVALID_ARGUMENT, "link_out / n_out is NULL");
+    const int64_t nv = (int64_t)grid->reso[0] * grid->reso[1] * grid->reso[2];
+    if (link_out != grid->link) {
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(link_out), a1 = a0 + 4 * (uintptr_t)nv;
+        const uintptr_t b0 = reinterpret_cast<uintptr_t>(grid->link), b1 = b0 + 4 * (uintptr_t)nv;
+        if (a0 < b1 && b0 < a1) return fail(PXM_INVALID_ARGUMENT, "link_out partly overlaps grid.link");
+    }
+    if (grid->n_alloc > 0) {
+        if (!data_out) return fail(PXM_INVALID_ARGUMENT, "data_out is NULL");
+        if (reinterpret_cast<uintptr_t>(data_out) & 15)
+            return fail(PXM_INVALID_ARGUMENT, "data_out must be 16-byte aligned");
+        const uintptr_t bytes = (uintptr_t)grid->n_alloc * PXM_RECORD * 4;
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(data_out), b0 = reinterpret_cast<uintptr_t>(grid->data);
+        if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(PXM_INVALID_ARGUMENT, "data_out overlaps grid.data");
+    }
+    PXM_TRY(check_edit_ws(grid, ws, ws_bytes));
+    return launched(pxm::launch_prune(kgrid(grid), tau, link_out, data_out, n_out, ws, (hipStream_t)stream),
+                    "grid_prune");
+}
+
 }  // extern "C"

@@ -56,6 +56,8 @@ _lock = threading.Lock()
 EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
            "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_grid_rmsprop",
            "pxm_render_gn", "pxm_pose_gn",
+           "pxm_grid_edit_workspace_bytes", "pxm_grid_upsample_link", "pxm_grid_upsample_data",
+           "pxm_grid_prune",
            "pxm_workspace_bytes",
            "pxm_occupancy_words", "pxm_build_occupancy",
            "pxm_set_tuning", "pxm_get_tuning", "pxm_status_string", "pxm_last_error",
@@ -85,6 +87,11 @@ def lib():
         L.pxm_grid_rmsprop.argtypes = [i64, P, P, P, f32, f32, f32, f32, P]
         L.pxm_render_gn.argtypes = [G, R, O, P, P, P, P, P]
         L.pxm_pose_gn.argtypes = [i32, P, P, f32, P]
+        L.pxm_grid_edit_workspace_bytes.argtypes = [G]
+        L.pxm_grid_edit_workspace_bytes.restype = sz
+        L.pxm_grid_upsample_link.argtypes = [G, P, P, P, sz, P]
+        L.pxm_grid_upsample_data.argtypes = [G, P, i64, P, P]
+        L.pxm_grid_prune.argtypes = [G, f32, P, P, P, P, sz, P]
         L.pxm_occupancy_words.argtypes = [G]
         L.pxm_occupancy_words.restype = sz
         L.pxm_build_occupancy.argtypes = [G, P, sz, P]
@@ -98,7 +105,8 @@ def lib():
         L.pxm_status_string.restype = C.c_char_p
         L.pxm_last_error.restype = C.c_char_p
         for name in ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
-                     "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_set_tuning"):
+                     "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_set_tuning",
+                     "pxm_grid_upsample_link", "pxm_grid_upsample_data", "pxm_grid_prune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -403,6 +411,66 @@ def grid_rmsprop(data, grad_data, state, lr_density, lr_sh, alpha=0.95, eps=1e-8
     _check("grid_rmsprop", lib().pxm_grid_rmsprop(n, _ptr(data), _ptr(grad_data), _ptr(state),
                                                   float(lr_density), float(lr_sh), float(alpha),
                                                   float(eps), _stream(stream)))
+
+
+# ----------------------------------------------------------------------------
+# dynamic grid: coarse-to-fine growth and pruning
+# ----------------------------------------------------------------------------
+
+def grid_edit_workspace(grid: DeviceGrid) -> torch.Tensor:
+    """Scratch for grid_upsample / grid_prune on this grid (contents free)."""
+    n = int(lib().pxm_grid_edit_workspace_bytes(C.byref(grid.struct())))
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=grid.link.device)
+
+
+def _sync(stream):
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+
+
+def grid_upsample_link(grid: DeviceGrid, ws=None, stream=None):
+    """Link table of the doubled lattice and its record count (device int64)."""
+    g = grid.struct()
+    reso = tuple(2 * int(r) - 1 for r in grid.reso)
+    link = torch.empty(int(np.prod(reso)), dtype=torch.int32, device=grid.link.device)
+    n = torch.zeros(1, dtype=torch.int64, device=grid.link.device)
+    ws = grid_edit_workspace(grid) if ws is None else ws
+    _check("grid_upsample_link", lib().pxm_grid_upsample_link(
+        C.byref(g), _ptr(link), _ptr(n), _ptr(ws), ws.numel(), _stream(stream)))
+    return reso, link, n
+
+
+def grid_upsample(grid: DeviceGrid, ws=None, occupancy=True, stream=None) -> DeviceGrid:
+    """Coarse-to-fine growth: 2R - 1 vertices per axis, voxel size halved.
+    Synchronises `stream` once to read the fine record count."""
+    reso, link, n = grid_upsample_link(grid, ws, stream)
+    _sync(stream)
+    n_fine = int(n.item())
+    data = torch.empty((n_fine, REC), dtype=torch.float32, device=grid.link.device)
+    _check("grid_upsample_data", lib().pxm_grid_upsample_data(
+        C.byref(grid.struct()), _ptr(link), n_fine, _ptr(data), _stream(stream)))
+    out = DeviceGrid(reso, grid.aabb_min, float(np.float32(grid.voxel_size) / np.float32(2)), link, data)
+    if occupancy:
+        out.build_occupancy(stream)
+    return out
+
+
+def grid_prune(grid: DeviceGrid, tau: float, ws=None, in_place=False, occupancy=True,
+               stream=None) -> DeviceGrid:
+    """Drop records with density <= tau; survivors keep their order.  With
+    in_place the link table of `grid` itself is rewritten.  Synchronises
+    `stream` once to read the surviving count."""
+    g = grid.struct()
+    link = grid.link if in_place else torch.empty_like(grid.link)
+    data = torch.empty_like(grid.data)
+    n = torch.zeros(1, dtype=torch.int64, device=grid.link.device)
+    ws = grid_edit_workspace(grid) if ws is None else ws
+    _check("grid_prune", lib().pxm_grid_prune(C.byref(g), float(tau), _ptr(link), _ptr(data), _ptr(n),
+                                              _ptr(ws), ws.numel(), _stream(stream)))
+    _sync(stream)
+    out = DeviceGrid(grid.reso, grid.aabb_min, grid.voxel_size, link, data[:int(n.item())])
+    if occupancy:
+        out.build_occupancy(stream)
+    return out
 
 
 def set_tuning(block: int, variant: int):

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(pxm.EXPORTS) == set(names)
-    assert pxm.abi_version() == 3
+    assert pxm.abi_version() == 4
 
 
 def test_status_strings():
@@ -161,6 +161,46 @@ def test_tv_adam_and_tuning_checks():
     pxm.set_tuning(128, 1)
     assert pxm.get_tuning() == (128, 1)
     pxm.set_tuning(*before)
+
+
+def test_grid_edit_checks():
+    """Workspace sizing and host-side rejection of the dynamic-grid calls."""
+    L = pxm.lib()
+    g = good_grid()
+    need = L.pxm_grid_edit_workspace_bytes(C.byref(g))
+    # 15^3 fine vertices: flag words and word prefixes (106 words each), one chunk total
+    assert need == 2 * 512 + 256
+    big = good_grid()
+    big.n_alloc = 100_000
+    assert L.pxm_grid_edit_workspace_bytes(C.byref(big)) == 2 * 12544 + 256 + 400_000
+    bad = good_grid()
+    bad.reso[0] = 1
+    assert L.pxm_grid_edit_workspace_bytes(C.byref(bad)) == 0
+    WS = 0x100000            # 256-byte aligned, never dereferenced
+    up = L.pxm_grid_upsample_link
+    assert up(C.byref(g), FAKE, FAKE, WS, need - 1, None) == 4
+    assert up(C.byref(g), FAKE, FAKE, WS + 16, need, None) == 1
+    assert up(C.byref(g), None, FAKE, WS, need, None) == 1
+    assert up(C.byref(g), FAKE, None, WS, need, None) == 1
+    huge = good_grid()
+    huge.reso[:] = [1025, 1025, 1025]     # 2049^3 fine vertices > 2^31 - 1
+    assert up(C.byref(huge), FAKE, FAKE, WS, 1 << 40, None) == 2
+    ud = L.pxm_grid_upsample_data
+    assert ud(C.byref(g), FAKE, 0, None, None) == 0          # nothing to write
+    assert ud(C.byref(g), FAKE, -1, FAKE, None) == 1
+    assert ud(C.byref(g), FAKE, 15 ** 3 + 1, FAKE, None) == 1
+    assert ud(C.byref(g), FAKE, 10, FAKE + 4, None) == 1
+    assert ud(C.byref(g), None, 10, FAKE, None) == 1
+    pr = L.pxm_grid_prune
+    out = 0x200000
+    assert pr(C.byref(g), float("nan"), out, out, FAKE, WS, need, None) == 1
+    assert pr(C.byref(g), 0.0, None, out, FAKE, WS, need, None) == 1
+    assert pr(C.byref(g), 0.0, out, out, None, WS, need, None) == 1
+    assert pr(C.byref(g), 0.0, out, FAKE, FAKE, WS, need, None) == 1      # data_out is grid.data
+    assert pr(C.byref(g), 0.0, out, FAKE + 512, FAKE, WS, need, None) == 1  # overlaps it
+    assert pr(C.byref(g), 0.0, FAKE + 4, out, FAKE, WS, need, None) == 1   # link_out overlaps link
+    assert pr(C.byref(g), 0.0, out, out + 4, FAKE, WS, need, None) == 1    # misaligned data_out
+    assert pr(C.byref(g), 0.0, out, out, FAKE, WS, need - 1, None) == 4
 
 
 def test_binding_rejects_host_tensors():

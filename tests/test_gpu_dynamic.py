@@ -1,0 +1,164 @@
+"""Dynamic grid on the GPU (coarse-to-fine growth, pruning) against the oracle.
+
+Both edits are integer compaction plus exact FP64 arithmetic rounded once to
+FP32, so links, counts and records must match the oracle bit for bit.  At
+full size (the 256^3 room grown to 511^3) the oracle runs on crops: a fine
+vertex strictly inside a crop depends only on coarse cells inside it."""
+import dataclasses
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2307_03404_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_03404_amd import pxm
+    return pxm
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+@functools.lru_cache(maxsize=None)
+def _grids():
+    rng = np.random.default_rng(71)
+    tiny = synth.random_tiny_grid(rng, R=5, margin=1, occupancy=0.4)
+    tiny.link[0] = tiny.n_alloc - 1                   # a lattice corner: clipped cells
+    reso = (5, 9, 13)
+    mask = rng.random(int(np.prod(reso))) < 0.2
+    ragged = synth.grid_from_mask(reso, (-1.0, 0.0, 0.5), 0.125, mask,
+                                  rng.normal(0.5, 1.0, int(mask.sum())).astype(np.float32), rng)
+    ragged.data[:, 0] = np.where(rng.random(ragged.n_alloc) < 0.3, 0.0, ragged.data[:, 0])
+    empty = synth.grid_from_mask((6, 6, 6), (0.0, 0.0, 0.0), 0.5, np.zeros(216, bool),
+                                 np.zeros(0, np.float32), rng)
+    dense, _ = synth.sphere_grid(3, R=32)            # 63^3 fine vertices: many chunks
+    room, _ = synth.room_grid(1, 96, 4.0, 0.1)       # 191^3 fine vertices, sparse
+    return {"tiny": tiny, "ragged": ragged, "empty": empty, "dense32": dense, "room96": room}
+
+
+GRID_NAMES = ["tiny", "ragged", "empty", "dense32", "room96"]
+
+
+@pytest.mark.parametrize("name", GRID_NAMES)
+def test_upsample_bit_exact(name):
+    pxm = _dev()
+    g = _grids()[name]
+    print(f"upsample {name}: reso {g.reso}, {g.n_alloc} records", flush=True)
+    want = oracle.grid_upsample(g)
+    got = pxm.grid_upsample(pxm.grid_to_device(g))
+    torch.cuda.synchronize()
+    assert tuple(got.reso) == want.reso
+    assert np.float32(got.voxel_size) == want.voxel_size
+    np.testing.assert_array_equal(np_(got.link), want.link)
+    assert got.n_alloc == want.n_alloc
+    assert np.array_equal(np_(got.data), want.data)
+
+
+@pytest.mark.parametrize("name", GRID_NAMES)
+def test_prune_bit_exact(name):
+    pxm = _dev()
+    g = _grids()[name]
+    dens = g.data[:, 0] if g.n_alloc else np.zeros(1, np.float32)
+    taus = [float(np.median(dens)), 0.0, -np.inf, float(dens.max())]
+    dg = pxm.grid_to_device(g)
+    ws = pxm.grid_edit_workspace(dg)
+    for tau in taus:
+        print(f"prune {name}: tau {tau}", flush=True)
+        want = oracle.grid_prune(g, np.float32(tau))
+        got = pxm.grid_prune(dg, tau, ws=ws)
+        np.testing.assert_array_equal(np_(got.link), want.link)
+        assert got.n_alloc == want.n_alloc
+        assert np.array_equal(np_(got.data), want.data)
+    # in place: the input's link table is rewritten
+    want = oracle.grid_prune(g, np.float32(taus[0]))
+    got = pxm.grid_prune(dg, taus[0], ws=ws, in_place=True)
+    assert got.link.data_ptr() == dg.link.data_ptr()
+    np.testing.assert_array_equal(np_(dg.link), want.link)
+    assert np.array_equal(np_(got.data), want.data)
+
+
+def test_grown_map_renders_like_the_coarse_one():
+    """GPU forward on the grown map at twice the step (with the rebuilt
+    occupancy bitfield) reproduces the coarse GPU forward."""
+    pxm = _dev()
+    wl = synth.config1()
+    n = min(wl.rays.n_rays, 20_000)
+    wl = synth.subset_rays(wl, n)
+    g = pxm.grid_to_device(wl.grid)
+    fine = pxm.grid_upsample(g)
+    r = pxm.rays_to_device(wl.rays)
+    rgb0, d0, _ = pxm.render_forward(g, r, wl.opts)
+    opts2 = dataclasses.replace(wl.opts, step_vox=2 * wl.opts.step_vox)
+    rgb1, d1, _ = pxm.render_forward(fine, r, opts2)
+    torch.cuda.synchronize()
+    assert (np_(rgb0).sum(1) > 0).sum() > n // 10
+    np.testing.assert_allclose(np_(rgb1), np_(rgb0), rtol=0, atol=2e-5)
+    np.testing.assert_allclose(np_(d1), np_(d0), rtol=1e-5, atol=2e-5)
+
+
+def _crop(g, lo, L):
+    R = g.reso[0]
+    link = g.link.reshape(R, R, R)[lo[0]:lo[0] + L, lo[1]:lo[1] + L, lo[2]:lo[2] + L]
+    ids = np.unique(link[link >= 0])
+    remap = np.full(g.n_alloc, -1, np.int64)
+    remap[ids] = np.arange(ids.size)
+    sub = np.where(link >= 0, remap[np.maximum(link, 0)], -1).astype(np.int32).ravel()
+    return synth.Grid((L, L, L), g.aabb_min, g.voxel_size, sub, g.data[ids].copy())
+
+
+def test_upsample_full_size_room256():
+    """The 256^3 room (10% allocated) grown to 511^3: ids run in lattice
+    order, and on crops every fine vertex away from the crop's faces matches
+    the oracle's growth of the crop, allocation and record."""
+    pxm = _dev()
+    wl = synth.config2()
+    g = wl.grid
+    dg = pxm.grid_to_device(g)
+    fine = pxm.grid_upsample(dg)
+    torch.cuda.synchronize()
+    print(f"room256 -> {fine.reso}: {fine.n_alloc} records", flush=True)
+    link = np_(fine.link)
+    Rf = fine.reso[0]
+    assert Rf == 511
+    alloc = np.flatnonzero(link >= 0)
+    assert alloc.size == fine.n_alloc > g.n_alloc
+    assert np.array_equal(link[alloc], np.arange(alloc.size, dtype=np.int32))
+    data = np_(fine.data)
+    link3 = link.reshape(Rf, Rf, Rf)
+    rng = np.random.default_rng(72)
+    L = 24
+    checked = 0
+    for _ in range(6):
+        # crops that straddle allocated surfaces
+        v = np.unravel_index(rng.choice(np.flatnonzero(g.link >= 0)), g.reso)
+        lo = [int(np.clip(c - L // 2, 0, g.reso[0] - L)) for c in v]
+        want = oracle.grid_upsample(_crop(g, lo, L))
+        wl3 = want.link.reshape(2 * L - 1, 2 * L - 1, 2 * L - 1)[1:-1, 1:-1, 1:-1]
+        sl = tuple(slice(2 * c + 1, 2 * c + 2 * L - 2) for c in lo)
+        gl3 = link3[sl]
+        np.testing.assert_array_equal(gl3 >= 0, wl3 >= 0)
+        m = wl3 >= 0
+        assert np.array_equal(data[gl3[m]], want.data[wl3[m]])
+        checked += int(m.sum())
+    assert checked > 10_000
+
+
+def test_prune_full_size_room256():
+    pxm = _dev()
+    g = synth.config2().grid
+    dg = pxm.grid_to_device(g)
+    want = oracle.grid_prune(g, np.float32(0.0))
+    got = pxm.grid_prune(dg, 0.0)
+    print(f"room256 prune: {g.n_alloc} -> {got.n_alloc}", flush=True)
+    assert 0 < got.n_alloc < g.n_alloc
+    np.testing.assert_array_equal(np_(got.link), want.link)
+    assert np.array_equal(np_(got.data), want.data)

@@ -731,3 +731,13 @@ def test_prune_of_zero_records_leaves_renders_unchanged():
     rgb1, dep1, _, _ = oracle.render(p, rays, opts)
     np.testing.assert_allclose(rgb1, rgb0, rtol=0, atol=1e-13)
     np.testing.assert_allclose(dep1, dep0, rtol=0, atol=1e-13)
+
+
+def test_dynamic_grid_edits_of_an_empty_map():
+    rng = np.random.default_rng(67)
+    g = synth.grid_from_mask((4, 5, 6), (0.0, 0.0, 0.0), 0.5, np.zeros(120, bool),
+                             np.zeros(0, np.float32), rng)
+    p = oracle.grid_prune(g, 0.0)
+    assert p.n_alloc == 0 and np.all(p.link == -1)
+    f = oracle.grid_upsample(g)
+    assert f.reso == (7, 9, 11) and f.n_alloc == 0 and np.all(f.link == -1)
