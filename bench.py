@@ -266,6 +266,95 @@ def compare_per_frame(wl, g, r, trgb, tdep, fw, steps, warmup):
             "speedup_vs_per_frame_unfused": tu / tb}
 
 
+def grid_edit_bench(args):
+    """Dynamic-grid edits on the resident 256^3 room (10 % allocated): prune
+    at tau = 0, then grow to 511^3 (link table, then records).  Each launch
+    group is bracketed by HIP events on the stream it runs on."""
+    import ctypes as C
+    import torch
+    from paper_2307_03404_amd import pxm, synth
+    wl = synth.config2()
+    g = pxm.grid_to_device(wl.grid, occupancy=False)
+    L = pxm.lib()
+    gs = g.struct()
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    ws = pxm.grid_edit_workspace(g)
+    Rf = tuple(2 * r - 1 for r in g.reso)
+    nc, nf, na = int(np.prod(g.reso)), int(np.prod(Rf)), g.n_alloc
+    link_f = torch.empty(nf, dtype=torch.int32, device="cuda")
+    n_f = torch.zeros(1, dtype=torch.int64, device="cuda")
+    link_p = torch.empty_like(g.link)
+    data_p = torch.empty_like(g.data)
+    n_p = torch.zeros(1, dtype=torch.int64, device="cuda")
+    P = pxm._ptr
+
+    def prune():
+        pxm._check("prune", L.pxm_grid_prune(C.byref(gs), 0.0, P(link_p), P(data_p), P(n_p), P(ws),
+                                             ws.numel(), sp))
+
+    def grow_link():
+        pxm._check("upsample_link", L.pxm_grid_upsample_link(C.byref(gs), P(link_f), P(n_f), P(ws),
+                                                             ws.numel(), sp))
+
+    grow_link()
+    prune()
+    torch.cuda.synchronize()
+    n_fine, n_kept = int(n_f.item()), int(n_p.item())
+    data_f = torch.empty((n_fine, pxm.REC), dtype=torch.float32, device="cuda")
+
+    def grow_data():
+        pxm._check("upsample_data", L.pxm_grid_upsample_data(C.byref(gs), P(link_f), n_fine, P(data_f), sp))
+
+    ops = {"prune": prune, "grow_link": grow_link, "grow_data": grow_data}
+    for _ in range(args.warmup):
+        for f in ops.values():
+            f()
+    torch.cuda.synchronize()
+    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)] for k in ops}
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        for k, f in ops.items():
+            ev[k][i][0].record(stream)
+            f()
+            ev[k][i][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    # algorithmic bytes: every input read once, every output written once
+    alg = {"prune": 4 * nc * 2 + 112 * na + 112 * n_kept,
+           "grow_link": 4 * nc + 4 * nf,
+           "grow_data": 4 * nf + 4 * nc + 112 * na + 112 * n_fine}
+    gbs = {k: alg[k] / (ms[k] * 1e-3) / 1e9 for k in ops}
+    total_ms = sum(ms.values())
+    achieved = sum(alg.values()) / (total_ms * 1e-3) / 1e9
+    return {
+        "metric": "dynamic-grid edit: prune + grow 256^3 -> 511^3, fine lattice vertices/s",
+        "value": nf * args.steps / elapsed,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 records, f64 interpolation, int32 links",
+        "data": "synthetic",
+        "config": {"workload": "c2_room256_grid_edit", "grid": list(g.reso), "fine_grid": list(Rf),
+                   "allocated_vertices": na, "kept_after_prune": n_kept, "fine_records": n_fine,
+                   "step": "prune (tau 0), grow link table, grow records"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "prune + grow_link + grow_data", "kernel_ms": total_ms,
+                     "alg_bytes_per_launch": sum(alg.values())},
+        "kernels_ms": ms,
+        "kernels_gbs": gbs,
+        "alg_bytes": alg,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +369,8 @@ def main():
                     help="time one batched fused launch against per-frame launches instead")
     ap.add_argument("--gauss-newton", action="store_true",
                     help="tracking workloads: Gauss-Newton iterations instead of Adam")
+    ap.add_argument("--grid-edit", action="store_true",
+                    help="time the dynamic-grid edits (prune, grow 256^3 -> 511^3) instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -295,6 +386,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.grid_edit:
+        print(json.dumps(grid_edit_bench(args)), flush=True)
         return
 
     t0 = time.perf_counter()

@@ -317,9 +317,8 @@ int pxm_grid_rmsprop(int64_t n_alloc, float* data, float* grad_data, float* stat
 
 size_t pxm_grid_edit_workspace_bytes(const pxm_grid* grid) {
     if (check_grid(grid, false) != PXM_OK) return 0;
-    const int64_t nf = (int64_t)(2 * grid->reso[0] - 1) * (2 * grid->reso[1] - 1) * (2 * grid->reso[2] - 1);
-    const size_t up = pxm::compaction_bytes(nf);
-    const size_t pr = pxm::compaction_bytes(grid->n_alloc) + 4 * (size_t)grid->n_alloc;
+    const size_t up = pxm::grow_workspace_bytes(grid->reso);
+    const size_t pr = pxm::prune_workspace_bytes(grid->n_alloc);
     return up > pr ? up : pr;
 }
 

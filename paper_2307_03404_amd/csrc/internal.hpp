@@ -46,10 +46,12 @@ hipError_t launch_pose_gn(int F, float* c2w, double* gn, float mu, hipStream_t s
 hipError_t launch_rmsprop(int64_t n, float* data, float* grad, float* avg, float lr_d, float lr_sh,
                           float alpha, float eps, hipStream_t st);
 
-// Dynamic-grid edits.  A compaction over n items takes compaction_bytes(n)
-// of workspace; pruning also keeps an int32 remap entry per record after it.
-constexpr int EDIT_CHUNK = 2048;
-size_t compaction_bytes(int64_t n);
+// Dynamic-grid edits: flags are compacted in chunks of EDIT_CHUNK items
+// (one workgroup).  Workspace bytes of a prune of n_alloc records and of the
+// growth of an R[0] x R[1] x R[2] lattice.
+constexpr int EDIT_CHUNK = 8192;
+size_t prune_workspace_bytes(int64_t n_alloc);
+size_t grow_workspace_bytes(const int R[3]);
 hipError_t launch_upsample_link(const KGrid& g, int32_t* link_fine, int64_t* n_fine, void* ws, hipStream_t st);
 hipError_t launch_upsample_data(const KGrid& g, const int32_t* link_fine, int64_t n_fine, float* data_fine,
                                 hipStream_t st);

@@ -168,8 +168,8 @@ def test_grid_edit_checks():
     L = pxm.lib()
     g = good_grid()
     need = L.pxm_grid_edit_workspace_bytes(C.byref(g))
-    # 15^3 fine vertices: flag words and word prefixes (106 words each), one chunk total
-    assert need == 2 * 512 + 256
+    # coarse row bits (64 rows x 1 word), 15 x 15 fine rows x 1 word of flags and of prefixes, one chunk total
+    assert need == 256 + 2 * 1024 + 256
     big = good_grid()
     big.n_alloc = 100_000
     assert L.pxm_grid_edit_workspace_bytes(C.byref(big)) == 2 * 12544 + 256 + 400_000

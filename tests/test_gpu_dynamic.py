@@ -40,12 +40,17 @@ def _grids():
     ragged.data[:, 0] = np.where(rng.random(ragged.n_alloc) < 0.3, 0.0, ragged.data[:, 0])
     empty = synth.grid_from_mask((6, 6, 6), (0.0, 0.0, 0.0), 0.5, np.zeros(216, bool),
                                  np.zeros(0, np.float32), rng)
+    reso = (4, 5, 70)                                  # flag windows across z words
+    mask = rng.random(int(np.prod(reso))) < 0.05
+    long_z = synth.grid_from_mask(reso, (0.0, 0.0, 0.0), 0.1, mask,
+                                  rng.random(int(mask.sum())).astype(np.float32), rng)
     dense, _ = synth.sphere_grid(3, R=32)            # 63^3 fine vertices: many chunks
     room, _ = synth.room_grid(1, 96, 4.0, 0.1)       # 191^3 fine vertices, sparse
-    return {"tiny": tiny, "ragged": ragged, "empty": empty, "dense32": dense, "room96": room}
+    return {"tiny": tiny, "ragged": ragged, "empty": empty, "long_z": long_z, "dense32": dense,
+            "room96": room}
 
 
-GRID_NAMES = ["tiny", "ragged", "empty", "dense32", "room96"]
+GRID_NAMES = ["tiny", "ragged", "empty", "long_z", "dense32", "room96"]
 
 
 @pytest.mark.parametrize("name", GRID_NAMES)
