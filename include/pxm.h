@@ -265,7 +265,7 @@ size_t pxm_occupancy_words(const pxm_grid *grid);
 int pxm_build_occupancy(const pxm_grid *grid, uint32_t *occ, size_t n_words, void *stream);
 
 /*
- * Dynamic grid (Sec. 5: a dynamic voxel grid with a peak resolution of
+ * Dynamic grid (Sec. 6.1: a dynamic voxel grid with a peak resolution of
  * 512^3; the paper gives no growth or pruning policy, so the schedule is the
  * caller's).  Both edits write a new link table and a new payload; the
  * caller then rebuilds the occupancy bitfield of the new grid.

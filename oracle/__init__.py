@@ -11,7 +11,7 @@ mapping, and the dynamic-grid edits: coarse-to-fine growth and pruning).
 Parity unpinned by the paper: the colour activation, the SH sign/order
 convention, the se(3) pose parametrisation, the default (position-only)
 pose chain, early termination, the TV regulariser and the growth/pruning
-rules of the dynamic grid (the paper names a dynamic grid with a 512^3 peak
+rules of the dynamic grid (Sec. 6.1 names a dynamic grid with a 512^3 peak
 and gives no policy) are readings; they are
 pinned by finite differences, closed forms and invariants, not by numbers
 the paper prints (it prints none for this path).
@@ -356,7 +356,8 @@ def rmsprop_grid(data, grad, state, lr_density, lr_sh, alpha, eps):
 
 
 def grid_upsample(grid):
-    """Coarse-to-fine growth of the map: the lattice of R vertices per axis
+    """Coarse-to-fine growth of the dynamic grid (Sec. 6.1; the rule is a
+    reading, the paper gives none): the lattice of R vertices per axis
     becomes 2R - 1, fine vertex 2v sitting on coarse vertex v (voxel size
     halved, same origin).  A fine vertex is allocated when it lies in (the
     closure of) a coarse cell with an allocated corner, in lattice order;
@@ -415,9 +416,10 @@ def grid_upsample(grid):
 
 
 def grid_prune(grid, tau):
-    """Prune the map: records whose density is <= tau are dropped, the others
-    keep their order and are renumbered, and the link table is rewritten
-    (a dropped vertex becomes empty).  Returns a new grid."""
+    """Prune the dynamic grid (Sec. 6.1; the rule is a reading): records
+    whose density is <= tau are dropped, the others keep their order and
+    are renumbered, and the link table is rewritten (a dropped vertex
+    becomes empty).  Returns a new grid."""
     import dataclasses
     data = np.asarray(grid.data)
     keep = data[:, 0] > np.float32(tau)

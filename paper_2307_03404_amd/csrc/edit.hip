@@ -1,4 +1,4 @@
-// Dynamic-grid edits: coarse-to-fine growth and pruning (Sec. 5: the map is
+// Dynamic-grid edits: coarse-to-fine growth and pruning (Sec. 6.1: the map is
 // a dynamic voxel grid that grows to a peak of 512^3).
 //
 // Both edits are stream compactions: a flag per item, an exclusive prefix
