@@ -20,7 +20,10 @@
 // survive in L2 between chunks; one workgroup per 4^3 brick made the launch
 // dispatch-bound on sparse 512^3 grids.)  Blocks are dealt to XCDs in
 // contiguous runs so that halos shared with neighbours are read through the
-// same L2.
+// same L2.  Each phase issues all of a thread's global loads before it uses
+// any (links, staged records, gradient entries), so a phase costs one memory
+// round trip: the gradient read-modify-writes, one per item in turn, were the
+// longest chain.
 #include "internal.hpp"
 
 namespace pxm {
@@ -33,6 +36,8 @@ constexpr int TH = TB + 2;
 constexpr int TH3 = TH * TH * TH;       // 216 staged positions
 constexpr int PLANE = TH3 + 1;          // padded field plane: lanes over fields hit distinct banks
 constexpr int TV_THREADS = 256;
+constexpr int TV_ITEMS = TB * TB * TB * 32 / TV_THREADS;   // vertex-field items per thread, at most
+constexpr int STAGE_ITERS = (TH3 * 7 + TV_THREADS - 1) / TV_THREADS;   // staged float4 per thread
 
 __device__ __forceinline__ int hidx8(int x, int y, int z) { return (x * TH8 + y) * TH8 + z; }
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (x * TH + y) * TH + z; }
@@ -56,15 +61,24 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
         const int c[3] = {x0, y0, z0};
         if (brick_empty(g, c)) return;                      // workgroup-uniform
     }
-    for (int p = t; p < TH83; p += TV_THREADS) {
-        const int hx = p / (TH8 * TH8), hy = (p / TH8) % TH8, hz = p % TH8;
-        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-        int id = -1;
-        if (x >= 0 && x < X && y >= 0 && y < Y && z >= 0 && z < Z) {
-            id = g.link[((int64_t)x * Y + y) * Z + z];
-            id = ((uint32_t)id < (uint64_t)g.n_alloc) ? id : -1;
+    {
+        // all of a thread's link loads are issued before the first LDS write
+        constexpr int LINK_ITERS = (TH83 + TV_THREADS - 1) / TV_THREADS;
+        int ids[LINK_ITERS];
+#pragma unroll
+        for (int k = 0; k < LINK_ITERS; ++k) {
+            const int p = t + k * TV_THREADS;
+            const int hx = p / (TH8 * TH8), hy = (p / TH8) % TH8, hz = p % TH8;
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+            ids[k] = -1;
+            if (p < TH83 && x >= 0 && x < X && y >= 0 && y < Y && z >= 0 && z < Z)
+                ids[k] = g.link[((int64_t)x * Y + y) * Z + z];
         }
-        s_id8[p] = id;
+#pragma unroll
+        for (int k = 0; k < LINK_ITERS; ++k) {
+            const int p = t + k * TV_THREADS;
+            if (p < TH83) s_id8[p] = ((uint32_t)ids[k] < (uint64_t)g.n_alloc) ? ids[k] : -1;
+        }
     }
     __syncthreads();
 #pragma unroll 1
@@ -85,28 +99,57 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             __syncthreads();                                // s_n and s_list are rewritten next
             continue;
         }
-        // stage the sub-halo links and records: 7 lanes per position, one float4 each
-        for (int i = t; i < TH3 * 7; i += TV_THREADS) {
-            const int p = i / 7, q = i - 7 * p;
-            const int hx = p / (TH * TH), hy = (p / TH) % TH, hz = p % TH;
-            const int id = s_id8[hidx8(ox + hx, oy + hy, oz + hz)];
-            if (q == 0) s_id[p] = id;
-            const float4 w = id >= 0 ? reinterpret_cast<const float4*>(g.data + (int64_t)id * REC)[q]
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-            s_v[4 * q][p] = w.x;
-            s_v[4 * q + 1][p] = w.y;
-            s_v[4 * q + 2][p] = w.z;
-            s_v[4 * q + 3][p] = w.w;
+        // stage the sub-halo links and records: 7 lanes per position, one
+        // float4 each; all of a thread's loads are issued before its LDS writes
+        float4 wv[STAGE_ITERS];
+#pragma unroll
+        for (int k = 0; k < STAGE_ITERS; ++k) {
+            const int i = t + k * TV_THREADS;
+            wv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < TH3 * 7) {
+                const int p = i / 7, q = i - 7 * p;
+                const int hx = p / (TH * TH), hy = (p / TH) % TH, hz = p % TH;
+                const int id = s_id8[hidx8(ox + hx, oy + hy, oz + hz)];
+                if (q == 0) s_id[p] = id;
+                if (id >= 0) wv[k] = reinterpret_cast<const float4*>(g.data + (int64_t)id * REC)[q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < STAGE_ITERS; ++k) {
+            const int i = t + k * TV_THREADS;
+            if (i < TH3 * 7) {
+                const int p = i / 7, q = i - 7 * p;
+                s_v[4 * q][p] = wv[k].x;
+                s_v[4 * q + 1][p] = wv[k].y;
+                s_v[4 * q + 2][p] = wv[k].z;
+                s_v[4 * q + 3][p] = wv[k].w;
+            }
         }
         __syncthreads();
-        // 32 lanes per allocated vertex, lane m < 28 takes field m
-        for (int it = t; it < n * 32; it += TV_THREADS) {
+        // 32 lanes per allocated vertex, lane m < 28 takes field m.  A thread
+        // has at most TV_ITEMS items (n <= 64); their gradient entries are
+        // read first, so the read-modify-writes cost one round trip, not one each.
+        float gv[TV_ITEMS];
+        int64_t ga[TV_ITEMS];
+#pragma unroll
+        for (int k = 0; k < TV_ITEMS; ++k) {
+            const int it = t + k * TV_THREADS;
             const int m = it & 31;
-            if (m >= REC) continue;
+            ga[k] = -1;
+            gv[k] = 0.f;
+            if (it < n * 32 && m < REC) {
+                ga[k] = (int64_t)s_id[s_list[it >> 5]] * REC + m;
+                gv[k] = grad[ga[k]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TV_ITEMS; ++k) {
+            if (ga[k] < 0) continue;
+            const int it = t + k * TV_THREADS;
+            const int m = it & 31;
             const int c = s_list[it >> 5];
             const int ix = c / (TH * TH), iy = (c / TH) % TH, iz = c % TH;
             const int x = x0 + ox + ix - 1, y = y0 + oy + iy - 1, z = z0 + oz + iz - 1;
-            const int id = s_id[c];
             const float* plane = s_v[m];
             auto val = [&](int p) -> float { return plane[p]; };
             const float lam = m == 0 ? lam_d : lam_sh;
@@ -139,7 +182,7 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
                 const float dz = v0 - c0;
                 acc += dz * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            grad[(int64_t)id * REC + m] += lam * acc;
+            grad[ga[k]] = gv[k] + lam * acc;
         }
         __syncthreads();                                    // LDS reused by the next sub-brick
     }
