@@ -14,6 +14,8 @@
 """
 from __future__ import annotations
 
+import dataclasses
+
 import json
 import os
 import time
@@ -280,6 +282,29 @@ class MappingLoop:
         valid = torch.isfinite(depth) & (depth > 0)
         w = (1.0 / valid.sum().clamp(min=1).to(torch.float32)).expand(F).contiguous()
         return idx, rays, rgb, depth, w
+
+    def grow(self):
+        """Coarse-to-fine growth of the map (Sec. 6.1's dynamic grid; see
+        pxm.grid_upsample): the voxel size halves while step_vox stays, so
+        samples along a ray become twice as dense, and max_samples doubles
+        to keep covering the same distance.  The records are new, so the
+        RMSProp running averages restart at zero."""
+        self.grid = pxm.grid_upsample(self.grid)
+        self.opts = dataclasses.replace(self.opts, max_samples=min(2 * int(self.opts.max_samples),
+                                                                   2 ** 31 - 1))
+        self._new_records()
+        return self.grid
+
+    def prune(self, tau):
+        """Drop the records with density <= tau (pxm.grid_prune); the
+        running averages restart at zero."""
+        self.grid = pxm.grid_prune(self.grid, tau)
+        self._new_records()
+        return self.grid
+
+    def _new_records(self):
+        self.grad = torch.zeros_like(self.grid.data)
+        self.state = torch.zeros_like(self.grid.data)
 
     def step(self, indices=None):
         idx, rays, rgb, depth, w = self.sample(indices)

@@ -110,3 +110,36 @@ def test_mapping_loop_reduces_loss_and_improves_psnr():
           f"L1 depth {l10:.4f} -> {l11:.4f}", flush=True)
     assert np.mean(losses[-10:]) < 0.7 * np.mean(losses[:5])
     assert psnr1 > psnr0 + 1.5
+
+
+def test_mapping_loop_grows_and_prunes_the_map():
+    """Map, grow the map to the doubled lattice, map on, prune, map on: the
+    grown map renders like the coarse one (finer sampling only), and the
+    loop keeps improving it after each edit."""
+    from paper_2307_03404_amd.batch import MappingLoop, image_metrics
+    pxm = _dev()
+    wl, start, g, kf, trgb, tdep = _c1_mapping()
+    psnr0, _ = image_metrics(g, kf, wl.opts, trgb, tdep)
+    loop = MappingLoop(g, kf, trgb, tdep, wl.opts, n_rays=2048, lr_density=0.05, lr_sh=0.005,
+                       alpha=0.95, eps=1e-8, tv=(0.0, 0.0, 1e-9), seed=5)
+    for _ in range(100):
+        loop.step()
+    psnr_a, _ = image_metrics(loop.grid, kf, loop.opts, trgb, tdep)
+    n_a = loop.grid.n_alloc
+    loop.grow()
+    assert tuple(loop.grid.reso) == (63, 63, 63) and loop.grid.n_alloc > n_a
+    psnr_b, _ = image_metrics(loop.grid, kf, loop.opts, trgb, tdep)
+    losses = [float(loop.step()) for _ in range(100)]
+    psnr_c, _ = image_metrics(loop.grid, kf, loop.opts, trgb, tdep)
+    n_c = loop.grid.n_alloc
+    loop.prune(0.0)
+    n_d = loop.grid.n_alloc
+    losses += [float(loop.step()) for _ in range(50)]
+    psnr_d, _ = image_metrics(loop.grid, kf, loop.opts, trgb, tdep)
+    print(f"PSNR {psnr0:.2f} -> {psnr_a:.2f} (32^3) -> grow {psnr_b:.2f} -> {psnr_c:.2f} (63^3, "
+          f"{n_c} records) -> prune to {n_d} -> {psnr_d:.2f} dB", flush=True)
+    assert abs(psnr_b - psnr_a) < 1.0            # growth keeps the field; sampling is finer
+    assert psnr_c > psnr_b - 0.1                 # mapping goes on at the new resolution
+    assert 0 < n_d < n_c
+    assert np.all(np.isfinite(losses))
+    assert psnr_d > psnr0 + 1.5
