@@ -8,7 +8,8 @@ import pytest
 
 import oracle
 from paper_2307_03404_amd import synth
-from tests._parity import TAU_FWD, TAU_GRAD, align_depth_decisions, assert_pose, assert_r28
+from tests._parity import (TAU_FWD, TAU_GRAD, align_depth_decisions, assert_pose, assert_r28,
+                           r28_ratio)
 
 pytestmark = pytest.mark.gpu
 
@@ -228,6 +229,29 @@ def c3():
 def test_fused_c3_tracking_all_frames(c3):
     """16 frames, 2k-50k rays each, one launch, per-frame pose reduction."""
     _fused_check(c3, 2, "c3 pose")
+
+
+def test_fused_view_direction_pose_term(c1):
+    """The exact view-direction pose term (PXM_FLAG_POSE_VIEWDIR) in the fused
+    kernel, grid + pose and pose only, against the oracle with the same flag."""
+    wl, _ = c1
+    wlv = wl.replace(opts=dataclasses.replace(wl.opts, flags=synth.FLAG_POSE_VIEWDIR))
+    ref = oracle.fused(wlv.grid, wlv.rays, wlv.targets, wlv.opts)
+    plain = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
+    # the term moves the rotation gradient well beyond the tolerance: a kernel
+    # that ignored the flag would fail
+    assert r28_ratio(plain["grad_pose"][:, 3:], ref["grad_pose"][:, 3:]) > 10 * TAU_GRAD
+    _fused_check(wlv, 3, "c1 grid+pose viewdir", ref)
+    _fused_check(wlv, 2, "c1 pose viewdir", ref)
+
+
+def test_fused_c3_tracking_view_direction(c3):
+    sub = synth.subset_rays(c3, 40000, seed=12)
+    subv = sub.replace(opts=dataclasses.replace(sub.opts, flags=synth.FLAG_POSE_VIEWDIR))
+    ref = oracle.fused(subv.grid, subv.rays, subv.targets, subv.opts, want_grid=False)
+    plain = oracle.fused(sub.grid, sub.rays, sub.targets, sub.opts, want_grid=False)
+    assert r28_ratio(plain["grad_pose"][:, 3:], ref["grad_pose"][:, 3:]) > 10 * TAU_GRAD
+    _fused_check(subv, 2, "c3 pose viewdir", ref)
 
 
 def test_fused_frames_with_no_rays(c3):
