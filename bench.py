@@ -7,7 +7,8 @@ batch: ray generation, sampling, gathers, compositing, loss, grid gradient
 (mapping) and pose gradient (tracking) in one fused launch, the TV gradient,
 and the Adam pose update.  Inputs are resident in HBM before timing starts.
 
-Prints ONE JSON line (see the design doc for every field).
+Prints ONE JSON line: the metric, throughput and step time, the roofline of the
+dominant kernel and the FP64 oracle's rate on this host.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload c2]
 """
@@ -375,8 +376,8 @@ def main():
                     help="only run 1 GiB device copies (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -409,9 +410,7 @@ def main():
         pxm.set_tuning(args.block or 256, max(args.variant, 0))
     else:
         from paper_2307_03404_amd.batch import Autotuner
-        cache = os.path.join(ROOT, "gpurun_out", "tune.json") if os.path.isdir(
-            os.path.join(ROOT, "gpurun_out")) else None
-        (b_, v_), tuned_ms = Autotuner(cache, reps=3, warmup=1).tune(
+        (b_, v_), tuned_ms = Autotuner(None, reps=3, warmup=1).tune(
             g, r, wl.opts, trgb, tdep, fw, want, force=True)
         log("autotuned launch shape: %d rays/workgroup, variant %d (%s)" % (
             b_, v_, ", ".join("%s: %.2f ms" % kv for kv in sorted(tuned_ms.items()))))

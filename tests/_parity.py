@@ -5,7 +5,7 @@ import numpy as np
 # elementwise with an RMS floor, |x - x*| <= tau * max(|x*|, rms(x*)).  The
 # floor lets entries that are tiny compared with the tensor's typical
 # magnitude (e.g. a vertex touched only by nearly transparent samples, whose
-# FP32 rounding is set by the large terms it is summed with) be judged
+# FP32 rounding is set by the large terms it is summed with) be measured
 # against that typical magnitude.  Atomic additions happen in any order, so
 # gradients cannot be bitwise reproducible.
 TAU_FWD = 1e-5

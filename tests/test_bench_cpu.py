@@ -1,0 +1,54 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
+byte model and the rule that HBM counters are reported only for the kernel
+sources, workload and launch shape they were taken on."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_algorithmic_bytes_per_launch():
+    # stats: occupied samples, allocated corners gathered, gradient corners, valid rays
+    stats = (10, 40, 30, 5)
+    assert bench.alg_bytes(stats, 7, 2, 2) == 44 * 7 + 32 * 10 + 112 * 40 + 24 * 2
+    assert bench.alg_bytes(stats, 7, 2, 3) == 44 * 7 + 32 * 10 + 112 * 40 + 24 * 2 + 224 * 30
+
+
+def _profile(tmp_path, sha, workload="wl", block=64, variant=1, traffic="123456"):
+    p = tmp_path / "traffic.md"
+    p.write_text("# counters\n\n"
+                 f"- workload: `{workload}`\n- block: `{block}`\n- variant: `{variant}`\n"
+                 f"- sources_sha256: `{sha}`\n- traffic_bytes_per_launch: `{traffic}`\n")
+    return str(p)
+
+
+def test_traffic_only_for_matching_sources_workload_and_launch(tmp_path, monkeypatch):
+    sha = bench.sources_sha256()
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, sha))
+    assert bench.measured_traffic("wl", 64, 1) == 123456.0
+    assert bench.measured_traffic("other", 64, 1) is None
+    assert bench.measured_traffic("wl", 128, 1) is None
+    assert bench.measured_traffic("wl", 64, 0) is None
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, "0" * 64))
+    assert bench.measured_traffic("wl", 64, 1) is None
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
+    assert bench.measured_traffic("wl", 64, 1) is None
+
+
+def test_sources_digest_covers_the_kernel_sources():
+    files = bench.KERNEL_SOURCES
+    assert "include/pxm.h" in files and "paper_2307_03404_amd/csrc" in files
+    d = bench.sources_sha256()
+    assert len(d) == 64 and d == bench.sources_sha256()
