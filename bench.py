@@ -111,16 +111,30 @@ def cpu_baseline(wl, budget_s=15.0, want_grid=True):
     probe = synth.subset_rays(wl, 4000, seed=21)
     t0 = time.perf_counter()
     oracle.fused(probe.grid, probe.rays, probe.targets, probe.opts, want_grid=want_grid)
-    dt = time.perf_counter() - t0
+    dt0 = dt = time.perf_counter() - t0
     n = int(min(wl.rays.n_rays, max(4000, 4000 * budget_s / max(dt, 1e-3))))
     sample = synth.subset_rays(wl, n, seed=22)
     t0 = time.perf_counter()
     oracle.fused(sample.grid, sample.rays, sample.targets, sample.opts, want_grid=want_grid)
     dt = time.perf_counter() - t0
     what = "grid+pose" if want_grid else "pose"
-    return {"value": n / dt, "unit": "rays/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} of {wl.rays.n_rays} rays (seeded uniform subset), fwd+loss+{what} "
-                      f"backward in FP64, {dt:.1f} s"}
+    out = {"value": n / dt, "unit": "rays/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{n} of {wl.rays.n_rays} rays (seeded uniform subset), fwd+loss+{what} "
+                     f"backward in FP64, {dt:.1f} s"}
+    # the same oracle on one thread, on a smaller sample of the same workload
+    cores = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        n1 = int(min(wl.rays.n_rays, max(500, 4000 * (budget_s / 3) / max(dt0 * cores, 1e-3))))
+        one = synth.subset_rays(wl, n1, seed=23)
+        t0 = time.perf_counter()
+        oracle.fused(one.grid, one.rays, one.targets, one.opts, want_grid=want_grid)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    out["single_thread"] = {"value": n1 / dt1, "unit": "rays/s", "cores": 1,
+                            "sample": f"{n1} rays (seeded uniform subset), {dt1:.1f} s"}
+    return out
 
 
 def tracking_bench(wl, g, r, trgb, tdep, fw, args):
@@ -469,7 +483,8 @@ def main():
         step(i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    fused_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    fused_times = [a.elapsed_time(b) for a, b in ev]
+    fused_ms = float(np.mean(fused_times))
     r.c2w.copy_(c2w0)
 
     # separate timing of the TV and pose-update kernels (reported, not used)
@@ -508,7 +523,7 @@ def main():
                      "kernel": "k_fused<true,true,false>", "kernel_ms": fused_ms,
                      "traffic_gbs": None if traffic is None else traffic / (fused_ms * 1e-3) / 1e9,
                      "alg_bytes_per_launch": bytes_launch},
-        "kernels_ms": {"fused": fused_ms, "tv": tv_ms},
+        "kernels_ms": {"fused": fused_ms, "fused_median": float(np.median(fused_times)), "tv": tv_ms},
         "autotune_ms": tuned_ms,
     }
     if not args.no_cpu_baseline:
