@@ -457,8 +457,9 @@ def grid_upsample(grid: DeviceGrid, ws=None, occupancy=True, stream=None) -> Dev
 def grid_prune(grid: DeviceGrid, tau: float, ws=None, in_place=False, occupancy=True,
                stream=None) -> DeviceGrid:
     """Drop records with density <= tau; survivors keep their order.  With
-    in_place the link table of `grid` itself is rewritten.  Synchronises
-    `stream` once to read the surviving count."""
+    in_place the link table of `grid` itself is rewritten, so `grid` (old
+    payload, new links) must not be used afterwards: use the returned grid.
+    Synchronises `stream` once to read the surviving count."""
     g = grid.struct()
     link = grid.link if in_place else torch.empty_like(grid.link)
     data = torch.empty_like(grid.data)
