@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define PXM_ABI_VERSION 4   /* 4: dynamic-grid growth and pruning */
+#define PXM_ABI_VERSION 5   /* 5: two-launch fused variant; per-ray workspace */
 #define PXM_RECORD 28          /* floats per vertex: density + 3 x 9 SH */
 
 typedef enum {
@@ -186,9 +186,12 @@ int pxm_tv_grad(const pxm_grid *grid, float lambda_density, float lambda_sh, flo
  *                 occupied samples, allocated corners of those, allocated
  *                 corners that received a gradient, rays with a valid target)
  * ws / ws_bytes: device workspace of at least pxm_workspace_bytes(..., want)
- *   bytes holding the tile-queue counters of the persistent launch form.  It
- *   must be zeroed before its first use; every call leaves it zeroed again.
- *   Calls that share one workspace must not run concurrently.
+ *   bytes, 256-byte aligned: the tile-queue counters of the persistent launch
+ *   forms (first 256 bytes), then the per-ray state that the two-launch form
+ *   hands from its forward launch to its backward launch (184 bytes per ray).
+ *   The counters must be zeroed before the first use; every call leaves them
+ *   zeroed again (the per-ray state needs no initialisation).  Calls that
+ *   share one workspace must not run concurrently.
  */
 int pxm_render_fused(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
                      const float *tgt_rgb, const float *tgt_depth, const float *frame_weight,
@@ -320,7 +323,8 @@ int pxm_grid_upsample_data(const pxm_grid *grid, const int32_t *link_fine, int64
 int pxm_grid_prune(const pxm_grid *grid, float tau, int32_t *link_out, float *data_out,
                    int64_t *n_out, void *ws, size_t ws_bytes, void *stream);
 
-/* Workspace bytes pxm_render_fused needs for these arguments and `want`. */
+/* Workspace bytes pxm_render_fused needs for these arguments and `want`, under
+ * any launch tuning: 256 + 184 * (n_rays rounded up to 64). */
 size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
                            int32_t want);
 
@@ -328,7 +332,10 @@ size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm
  * Launch tuning for pxm_render_fused (process-wide; read at each call):
  *   block    rays per workgroup (64, 128 or 256; 0 = default 256)
  *   variant  0 = one workgroup per ray tile, 1 = persistent workgroups
- *            pulling ray tiles from a device counter in the workspace
+ *            pulling ray tiles from a device counter in the workspace,
+ *            2 = two persistent launches: the forward and loss (few
+ *            registers, higher occupancy), then the backward resuming
+ *            from the per-ray state the first left in the workspace
  * Returns PXM_INVALID_ARGUMENT for values outside these sets.
  */
 int pxm_set_tuning(int32_t block, int32_t variant);

@@ -81,7 +81,7 @@ def pack_frames(frames, width: int, tile: int = 8) -> PackedRays:
 # autotuner
 # ----------------------------------------------------------------------------
 
-CANDIDATES = [(b, v) for b in (64, 128, 256) for v in (0, 1)]
+CANDIDATES = [(b, v) for b in (64, 128, 256) for v in (0, 1, 2)]
 
 
 def _signature(grid, rays, opts, want) -> str:

@@ -148,7 +148,7 @@ int pxm_set_tuning(int32_t block, int32_t variant) {
     if (block == 0) block = 256;
     if (block != 64 && block != 128 && block != 256)
         return fail(PXM_INVALID_ARGUMENT, "block = %d not in {64,128,256}", block);
-    if (variant != 0 && variant != 1) return fail(PXM_INVALID_ARGUMENT, "variant = %d not in {0,1}", variant);
+    if (variant < 0 || variant > 2) return fail(PXM_INVALID_ARGUMENT, "variant = %d not in {0,1,2}", variant);
     g_block.store(block);
     g_variant.store(variant);
     return PXM_OK;
@@ -236,8 +236,8 @@ int pxm_build_occupancy(const pxm_grid* grid, uint32_t* occ, size_t n_words, voi
 
 size_t pxm_workspace_bytes(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
                            int32_t want) {
-    (void)grid; (void)rays; (void)opts; (void)want;
-    return pxm::FUSED_WS_BYTES;
+    (void)grid; (void)opts; (void)want;
+    return pxm::fused_workspace_bytes(rays && rays->n_rays > 0 ? rays->n_rays : 0);
 }
 
 int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
@@ -257,6 +257,7 @@ int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts*
     if ((want & PXM_WANT_STATS) && !stats) return fail(PXM_INVALID_ARGUMENT, "stats is NULL");
     const size_t need = pxm_workspace_bytes(grid, rays, opts, want);
     if (!ws) return fail(PXM_INVALID_ARGUMENT, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(PXM_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
     if (ws_bytes < need) return fail(PXM_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, need);
     if (rays->n_rays == 0) return PXM_OK;
     const int block = g_block.load(), variant = g_variant.load();

@@ -9,8 +9,43 @@
 namespace pxm {
 
 // Fused-kernel workspace: tile counter and finished-workgroup counter of the
-// persistent variant.  The kernel leaves both at zero when it completes.
+// persistent variants (the kernel leaves both at zero when it completes),
+// then the per-ray state the two-launch variant hands from its forward
+// launch to its backward launch (arrays of n_pad entries, n_pad = n_rays
+// rounded up to 64): work-mask words [MARK_WORDS][n_pad] u32, FP64 colour
+// and range sums [4][n_pad], upstream gradients [4][n_pad] f32, samples to
+// replay [n_pad] i32 and mask extent [n_pad] i32.
 constexpr size_t FUSED_WS_BYTES = 256;
+constexpr size_t SPLIT_BYTES_PER_RAY = 32 * 4 + 4 * 8 + 4 * 4 + 4 + 4;
+
+struct KSplit {
+    uint32_t* marks;
+    double* sums;
+    float* up;
+    int32_t* nb;
+    int32_t* minfo;
+    int64_t n_pad;
+};
+
+inline int64_t split_pad(int64_t n_rays) { return (n_rays + 63) / 64 * 64; }
+inline size_t fused_workspace_bytes(int64_t n_rays) {
+    return FUSED_WS_BYTES + (size_t)split_pad(n_rays) * SPLIT_BYTES_PER_RAY;
+}
+inline KSplit split_state(void* ws, int64_t n_rays) {
+    KSplit k;
+    k.n_pad = split_pad(n_rays);
+    char* p = static_cast<char*>(ws) + FUSED_WS_BYTES;
+    k.sums = reinterpret_cast<double*>(p);
+    p += (size_t)k.n_pad * 4 * sizeof(double);
+    k.marks = reinterpret_cast<uint32_t*>(p);
+    p += (size_t)k.n_pad * 32 * sizeof(uint32_t);
+    k.up = reinterpret_cast<float*>(p);
+    p += (size_t)k.n_pad * 4 * sizeof(float);
+    k.nb = reinterpret_cast<int32_t*>(p);
+    p += (size_t)k.n_pad * sizeof(int32_t);
+    k.minfo = reinterpret_cast<int32_t*>(p);
+    return k;
+}
 
 hipError_t launch_forward(const KGrid& g, const KRays& rs, const KOpts& op, float* rgb,
                           float* depth, int32_t* nsamp, hipStream_t st);

@@ -43,7 +43,7 @@ struct FwdResult {
 // out.mark_overflow is set if a marked position lay beyond the mask.
 __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, const Ray& ray,
                                             const float Y[9], FwdResult& out,
-                                            uint32_t* marks = nullptr) {
+                                            uint32_t* marks = nullptr, int64_t mstride = WAVE) {
     // colour and range are summed in FP64: the backward differences them
     // with its own prefix sums (Eq. 9, 10), and in FP32 that difference
     // would carry rounding that grows with the number of samples
@@ -85,7 +85,7 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
                 } else {
                     const int w = (int)(o >> 5);
                     while (mw < w) {
-                        marks[mw * WAVE] = mbits;
+                        marks[mw * mstride] = mbits;
                         mbits = 0u;
                         ++mw;
                     }
@@ -115,7 +115,7 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
             if (T < op.t_stop) break;
         }
     }
-    if (marks) marks[mw * WAVE] = mbits;
+    if (marks) marks[mw * mstride] = mbits;
     out.mark_last = mw;
     out.mark_overflow = movf;
     out.Cd[0] = C0; out.Cd[1] = C1; out.Cd[2] = C2;
@@ -535,8 +535,12 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
     }
 }
 
-template <bool GRID, bool POSE, bool VIEW>
-__global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
+// Fused step, in one launch (PH 0) or split in two (PH 1: forward and loss,
+// PH 2: backward).  The forward launch needs no LDS and few registers, so it
+// runs at the occupancy of a forward-only kernel; it leaves each ray's work
+// mask and backward inputs in `sp`, from which the backward launch resumes.
+template <bool GRID, bool POSE, bool VIEW, int PH>
+__global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays rs, KOpts op,
                                                const float* __restrict__ tgt_rgb,
                                                const float* __restrict__ tgt_depth,
                                                const float* __restrict__ fw,
@@ -546,11 +550,12 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
                                                float* __restrict__ grad,
                                                double* __restrict__ grad_pose,
                                                int64_t* __restrict__ stats,
-                                               unsigned* __restrict__ ws, int persistent) {
+                                               unsigned* __restrict__ ws, int persistent,
+                                               KSplit sp) {
     __shared__ int64_t s_tile;
     extern __shared__ float smem[];
     WaveStage wc{nullptr, nullptr};
-    if (GRID) wc = wave_stage(smem);
+    if (GRID && PH != 1) wc = wave_stage(smem);
     const int64_t n_tiles = (rs.n + blockDim.x - 1) / blockDim.x;
     // Persistent form: workgroups take tiles in order from one queue counter
     // (ws[0]), so the tiles in flight at any time are neighbours in the
@@ -581,15 +586,40 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
         int nb = 0;
         fr.mark_last = 0;
         fr.mark_overflow = false;
-        uint32_t* marks = GRID ? wc.marks + lane_id()
+        uint32_t* marks = PH == 1 ? ((GRID || POSE) && inr ? sp.marks + r : nullptr)
+                        : GRID ? wc.marks + lane_id()
                         : POSE ? reinterpret_cast<uint32_t*>(smem) + (threadIdx.x / WAVE) * (MARK_WORDS * WAVE)
                                      + lane_id()
                                : nullptr;
-        if (inr) {
+        if (PH == 2) {
+            // resume from the forward launch: backward inputs and work mask
+            if (inr) {
+                f = frame_of(rs.off, rs.F, r);
+                setup_ray(g, rs, op, r, f, ray);
+                sh9(ray.d[0], ray.d[1], ray.d[2], Y);
+                const float Dt = tgt_depth[r];
+                valid = isfinite(Dt) && Dt > 0.f;
+                nb = sp.nb[r];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    fr.Cd[c] = sp.sums[c * sp.n_pad + r];
+                    gC[c] = sp.up[c * sp.n_pad + r];
+                }
+                fr.Dd = sp.sums[3 * sp.n_pad + r];
+                gDr = sp.up[3 * sp.n_pad + r];
+                const int mi = sp.minfo[r];
+                fr.mark_last = mi & 0xff;
+                fr.mark_overflow = (mi >> 8) != 0;
+                if (marks && !fr.mark_overflow)
+                    for (int w = 0; w <= fr.mark_last; ++w) marks[w * WAVE] = sp.marks[w * sp.n_pad + r];
+            } else {
+                fr.Cd[0] = fr.Cd[1] = fr.Cd[2] = fr.Dd = 0.0;
+            }
+        } else if (inr) {
             f = frame_of(rs.off, rs.F, r);
             setup_ray(g, rs, op, r, f, ray);
             sh9(ray.d[0], ray.d[1], ray.d[2], Y);
-            ray_forward(g, op, ray, Y, fr, marks);
+            ray_forward(g, op, ray, Y, fr, marks, PH == 1 ? sp.n_pad : (int64_t)WAVE);
             const float z = fr.D / ray.s;
             if (rgb_out) {
                 rgb_out[3 * r] = fr.C[0];
@@ -617,23 +647,35 @@ __global__ void __launch_bounds__(256) k_fused(KGrid g, KRays rs, KOpts op,
                 gDr = op.lambda_d * wf * drho / ray.s;
                 nb = fr.n;
             }
+            if (PH == 1) {
+                // hand the backward inputs to the backward launch
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sp.sums[c * sp.n_pad + r] = fr.Cd[c];
+                    sp.up[c * sp.n_pad + r] = gC[c];
+                }
+                sp.sums[3 * sp.n_pad + r] = fr.Dd;
+                sp.up[3 * sp.n_pad + r] = gDr;
+                sp.nb[r] = nb;
+                sp.minfo[r] = fr.mark_last | (fr.mark_overflow ? 0x100 : 0);
+            }
         } else {
             fr.C[0] = fr.C[1] = fr.C[2] = fr.D = 0.f;
             fr.Cd[0] = fr.Cd[1] = fr.Cd[2] = fr.Dd = 0.0;
         }
-        if (GRID || POSE)
+        if ((GRID || POSE) && PH != 1)
             ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, nb, fr.Cd, fr.Dd, gC, gDr, grad, wc, pa, marks,
                                            fr.mark_last, fr.mark_overflow);
-        if (loss) {
+        if (loss && PH != 2) {
             double lv[1] = {lval};
             seg_sum_atomic<1>(f, valid, lv, loss);
         }
-        if (POSE) {
+        if (POSE && PH != 1) {
             double six[6] = {0, 0, 0, 0, 0, 0};
             if (valid) pose_six<VIEW>(ray, pa, six);
             seg_sum_atomic<6>(f, valid, six, grad_pose);
         }
-        if (stats) {
+        if (stats && PH != 2) {
             long long sv[4] = {inr ? fr.occ : 0, inr ? fr.occ_corners : 0,
                                valid ? fr.grad_corners : 0, valid ? 1 : 0};
             add_stats(inr, sv, stats);
@@ -771,13 +813,13 @@ static int device_cus() {
 
 // Persistent grid: as many workgroups as the device holds at once (from the
 // kernel's register and LDS use), never more than there are tiles.
-template <bool GRID, bool POSE, bool VIEW>
+template <bool GRID, bool POSE, bool VIEW, int PH>
 static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
     static int per_cu[4] = {0, 0, 0, 0};                  // by block 64/128/256/512
     const int slot = block == 64 ? 0 : block == 128 ? 1 : block == 256 ? 2 : 3;
     if (per_cu[slot] <= 0) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW>, block, lds)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW, PH>, block, lds)
                 != hipSuccess || n <= 0)
             n = 1;
         per_cu[slot] = n;
@@ -787,17 +829,38 @@ static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
     return (unsigned)(tiles < cap ? tiles : cap);
 }
 
+template <bool GRID, bool POSE, bool VIEW, int PH>
+static void fused_phase(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
+                        const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
+                        const float* fw, float* rgb, float* depth, double* loss, float* grad,
+                        double* gp, int64_t* stats, unsigned* ws, int persistent, const KSplit& sp) {
+    const size_t lds = PH == 1 ? 0
+                     : GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float)
+                     : POSE ? (block.x / WAVE) * MARK_WORDS * WAVE * sizeof(uint32_t) : 0;
+    const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW, PH>(block.x, lds, tiles)
+                               : (unsigned)tiles);
+    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW, PH>), grid, block, lds, st, g, rs, op, tgt_rgb,
+                       tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent, sp);
+}
+
+// variant 0: one workgroup per tile; 1: persistent workgroups on the tile
+// queue; 2: a forward launch then a backward launch, both persistent, with
+// the per-ray state in the workspace
 template <bool GRID, bool POSE, bool VIEW>
 static void fused_go(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
                      const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                      const float* fw, float* rgb, float* depth, double* loss, float* grad,
-                     double* gp, int64_t* stats, unsigned* ws, int persistent) {
-    const size_t lds = GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float)
-                     : POSE ? (block.x / WAVE) * MARK_WORDS * WAVE * sizeof(uint32_t) : 0;
-    const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW>(block.x, lds, tiles)
-                               : (unsigned)tiles);
-    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW>), grid, block, lds, st, g, rs, op, tgt_rgb,
-                       tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent);
+                     double* gp, int64_t* stats, unsigned* ws, int variant) {
+    if (variant == 2) {
+        const KSplit sp = split_state(ws, rs.n);
+        fused_phase<GRID, POSE, VIEW, 1>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb, depth,
+                                         loss, grad, gp, stats, ws, 1, sp);
+        fused_phase<GRID, POSE, VIEW, 2>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb, depth,
+                                         loss, grad, gp, stats, ws, 1, sp);
+    } else {
+        fused_phase<GRID, POSE, VIEW, 0>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb, depth,
+                                         loss, grad, gp, stats, ws, variant, KSplit{});
+    }
 }
 
 hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,

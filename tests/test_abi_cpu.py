@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(pxm.EXPORTS) == set(names)
-    assert pxm.abi_version() == 4
+    assert pxm.abi_version() == 5
 
 
 def test_status_strings():
@@ -135,7 +135,10 @@ def test_backward_and_fused_argument_checks():
                               FAKE, 8, None) == 4
     assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 0, None, None, None, None, None, None,
                               None, 4096, None) == 1
-    assert L.pxm_workspace_bytes(*args, 3) >= 8
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 0, None, None, None, None, None, None,
+                              FAKE + 8, 1 << 20, None) == 1
+    # queue counters, then 184 bytes of per-ray state for n_rays rounded up to 64
+    assert L.pxm_workspace_bytes(*args, 3) == 256 + 64 * 184
 
 
 def test_tv_adam_and_tuning_checks():
@@ -156,8 +159,10 @@ def test_tv_adam_and_tuning_checks():
     assert L.pxm_grid_rmsprop(4, FAKE + 4, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8,
                               None) == 1
     assert L.pxm_set_tuning(100, 0) == 1
-    assert L.pxm_set_tuning(256, 2) == 1
+    assert L.pxm_set_tuning(256, 3) == 1
     before = pxm.get_tuning()
+    pxm.set_tuning(64, 2)
+    assert pxm.get_tuning() == (64, 2)
     pxm.set_tuning(128, 1)
     assert pxm.get_tuning() == (128, 1)
     pxm.set_tuning(*before)

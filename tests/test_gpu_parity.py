@@ -194,7 +194,7 @@ def test_fused_c1_grid_and_pose(c1):
     _fused_check(wl, 3, "c1 fused", ref)
 
 
-@pytest.mark.parametrize("block,variant", [(64, 0), (128, 1), (64, 1), (256, 1)])
+@pytest.mark.parametrize("block,variant", [(64, 0), (128, 1), (64, 1), (256, 1), (64, 2), (256, 2)])
 def test_fused_c1_launch_shapes(c1, block, variant):
     wl, ref = c1
     _fused_check(wl, 3, f"c1 b{block} v{variant}", ref, block, variant)
