@@ -67,10 +67,22 @@ def test_autotuner_picks_a_candidate_and_caches(tmp_path):
 
 
 @pytest.mark.gpu
-def test_tracking_graph_replays_match_eager_and_reduce_loss():
+@pytest.mark.parametrize("tuning", [(256, 0), (64, 2)])
+def test_tracking_graph_replays_match_eager_and_reduce_loss(tuning):
     """20 captured Adam iterations over 16 frames: every replay (with eager
-    work between replays) matches the eager run; the loss goes down."""
+    work between replays) matches the eager run; the loss goes down.  Also
+    with the two-launch variant, whose graph holds two launches per
+    iteration and hands per-ray state through the workspace."""
     pxm = _gpu()
+    old = pxm.get_tuning()
+    pxm.set_tuning(*tuning)
+    try:
+        _tracking_graph_check(pxm)
+    finally:
+        pxm.set_tuning(*old)
+
+
+def _tracking_graph_check(pxm):
     from paper_2307_03404_amd.batch import TrackingGraph
     wl = synth.config3()
     wl = synth.subset_rays(wl, 60000, seed=2)
