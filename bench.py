@@ -206,7 +206,9 @@ def tracking_bench(wl, g, r, trgb, tdep, fw, args):
                    "block": block, "variant": variant},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_gn<false>" if args.gauss_newton else "k_fused<false,true,false>",
+                     "kernel": ("k_gn<false>" if args.gauss_newton
+                                else "k_fused<false,true,false,1> + k_fused<false,true,false,2>"
+                                if variant == 2 else "k_fused<false,true,false,0>"),
                      "kernel_ms": kern_ms,
                      "alg_bytes_per_launch": bytes_launch},
         "graph_ms_median": graph_ms,
@@ -520,7 +522,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_fused<true,true,false>", "kernel_ms": fused_ms,
+                     "kernel": ("k_fused<true,true,false,1> + k_fused<true,true,false,2>"
+                                if variant == 2 else "k_fused<true,true,false,0>"),
+                     "kernel_ms": fused_ms,
                      "traffic_gbs": None if traffic is None else traffic / (fused_ms * 1e-3) / 1e9,
                      "alg_bytes_per_launch": bytes_launch},
         "kernels_ms": {"fused": fused_ms, "fused_median": float(np.median(fused_times)), "tv": tv_ms},
