@@ -37,11 +37,19 @@ def _frame(wl, f):
     return wl.replace(rays=rays, targets=tg), a, b
 
 
-def test_fused_mixed_64_frame_batch_full_size():
+@pytest.fixture(scope="module")
+def c5():
+    return synth.config5()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_fused_mixed_64_frame_batch_full_size(c5, variant):
+    """In one launch (variant 1) and in two (variant 2, the form the autotuner
+    picks for this batch)."""
     pxm = _dev()
-    wl = synth.config5()
+    wl = c5
     n, F = wl.rays.n_rays, wl.rays.n_frames
-    print(f"{wl.name}: {n} rays, {F} frames", flush=True)
+    print(f"{wl.name}: {n} rays, {F} frames, variant {variant}", flush=True)
     g = pxm.grid_to_device(wl.grid)
     r = pxm.rays_to_device(wl.rays)
     trgb = torch.from_numpy(wl.targets.rgb).cuda()
@@ -53,7 +61,7 @@ def test_fused_mixed_64_frame_batch_full_size():
     gd = torch.zeros_like(g.data)
     gp = torch.zeros(F, 6, dtype=torch.float64, device="cuda")
     old = pxm.get_tuning()
-    pxm.set_tuning(64, 1)
+    pxm.set_tuning(64, variant)
     try:
         ws = pxm.new_workspace(g, r, wl.opts, 3)
         pxm.render_fused(g, r, wl.opts, trgb, tdep, fw, 3, rgb=rgb, depth=depth, loss=loss,

@@ -353,9 +353,16 @@ def test_fused_c2_tiles_without_occupancy(c2):
     np.testing.assert_array_equal(outs[0][1], outs[1][1])      # same samples counted
 
 
-def test_fused_c2_full_frame(c2):
-    """The whole 816,000-ray frame at the bench launch configuration."""
-    _fused_check(c2, 3, "c2 full", block=64, variant=1)
+@pytest.fixture(scope="module")
+def c2_ref(c2):
+    return oracle.fused(c2.grid, c2.rays, c2.targets, c2.opts)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_fused_c2_full_frame(c2, c2_ref, variant):
+    """The whole 816,000-ray frame at the bench launch configuration (one
+    launch, persistent) and in the two-launch form."""
+    _fused_check(c2, 3, f"c2 full v{variant}", c2_ref, block=64, variant=variant)
 
 
 def test_tv_c2(c2):
