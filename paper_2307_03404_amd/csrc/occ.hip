@@ -18,32 +18,38 @@ void occ_layout(const int R[3], int64_t& w0_words, int& W0, int B[3], int64_t& w
     w1_words = ((int64_t)B[0] * B[1] * B[2] + 31) / 32;
 }
 
-__device__ __forceinline__ bool valid_link(const KGrid& g, int64_t l) {
-    return (uint32_t)g.link[l] < (uint64_t)g.n_alloc;
-}
-
-// One lane per level-0 word: 32 cells of one (x, y) row.
+// One lane per cell, z fastest along each (x, y) row of cells padded to W0
+// words; each lane requests its 8 corner links at once (neighbouring lanes
+// read neighbouring links), and a ballot per 64 cells writes two level-0
+// words.  The loop runs over a multiple of 64 cells so every wave reaches the
+// ballot whole.
 __global__ void k_occ0(KGrid g, uint32_t* __restrict__ occ0, int64_t nwords, int W0) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= nwords) return;
-    const int64_t row = w / W0;
-    const int z0 = (int)(w % W0) * 32;
-    const int cx = (int)(row / (g.R[1] - 1)), cy = (int)(row % (g.R[1] - 1));
-    const int64_t c00 = (int64_t)cx * g.sx + (int64_t)cy * g.sy;
-    // column (z) occupancy of the four corner lines, then cells = any(z, z+1)
-    auto column = [&](int z) -> bool {
-        return valid_link(g, c00 + z) || valid_link(g, c00 + g.sy + z) || valid_link(g, c00 + g.sx + z)
-            || valid_link(g, c00 + g.sx + g.sy + z);
-    };
-    uint32_t bits = 0;
-    bool prev = column(z0);
-    const int zend = min(z0 + 32, g.R[2] - 1);
-    for (int z = z0; z < zend; ++z) {
-        const bool next = column(z + 1);
-        if (prev || next) bits |= 1u << (z - z0);
-        prev = next;
+    const int64_t n_cells = nwords * 32;                    // including the row padding
+    const int64_t padded = (n_cells + WAVE - 1) / WAVE * WAVE;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int lane = lane_id();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded; i += stride) {
+        bool occ = false;
+        if (i < n_cells) {
+            const int64_t w = i >> 5;
+            const int64_t row = w / W0;
+            const int cz = (int)(w - row * W0) * 32 + (int)(i & 31);
+            if (cz < g.R[2] - 1) {
+                const int cx = (int)(row / (g.R[1] - 1)), cy = (int)(row % (g.R[1] - 1));
+                const int64_t c = (int64_t)cx * g.sx + (int64_t)cy * g.sy + cz;
+                int32_t l[8];
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    l[b] = g.link[c + ((b >> 2) & 1) * g.sx + ((b >> 1) & 1) * g.sy + (b & 1)];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) occ |= (uint32_t)l[b] < (uint64_t)g.n_alloc;
+            }
+        }
+        const unsigned long long m = __ballot(occ);
+        const int64_t w0 = (i - lane) >> 5;
+        if (lane == 0 && w0 < nwords) occ0[w0] = (uint32_t)m;
+        if (lane == 32 && w0 + 1 < nwords) occ0[w0 + 1] = (uint32_t)(m >> 32);
     }
-    occ0[w] = bits;
 }
 
 // One lane per brick; the wave's 64 bricks fill two level-1 words.
@@ -75,7 +81,10 @@ hipError_t launch_occupancy(const KGrid& g, uint32_t* occ, hipStream_t st) {
     int64_t w0, w1;
     int W0, B[3];
     occ_layout(g.R, w0, W0, B, w1);
-    hipLaunchKernelGGL(k_occ0, dim3((unsigned)((w0 + 255) / 256)), dim3(256), 0, st, g, occ, w0, W0);
+    const int64_t cells = w0 * 32;
+    const int64_t blocks0 = (cells + 255) / 256;
+    hipLaunchKernelGGL(k_occ0, dim3((unsigned)(blocks0 < (1 << 20) ? blocks0 : (1 << 20))), dim3(256), 0, st, g, occ,
+                       w0, W0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nb = (int64_t)B[0] * B[1] * B[2];
