@@ -597,3 +597,57 @@ def test_autograd_matches_direct_calls(c1):
     ref = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
     assert_r28(np_(data.grad), ref["grad_data"], TAU_GRAD, "autograd grid")
     assert_pose(np_(xi.grad), ref["grad_pose"], TAU_GRAD, "autograd pose")
+
+
+def _small_lattice_workload(reso, seed):
+    """A lattice at or near the minimum size: one cell (2x2x2), or two
+    vertices thick, seen by a 24x24 camera from outside the box."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(reso))
+    mask = np.ones(n, bool) if n == 8 else rng.random(n) < 0.6
+    sig = rng.uniform(0.2, 2.0, int(mask.sum())).astype(np.float32)
+    vs = 0.1
+    g = synth.grid_from_mask(reso, (0.0, 0.0, 0.0), vs, mask, sig, rng)
+    centre = vs * (np.array(reso, np.float64) - 1) / 2
+    eye = centre + np.array([0.35, -0.3, 0.25]) * (0.5 + max(reso) * vs)
+    c2w = synth.look_at(eye, centre)
+    W = 24
+    intr = np.array([W, W, W / 2, W / 2], np.float64)
+    v_, u_ = np.mgrid[0:W, 0:W]
+    pix = np.stack([u_.ravel(), v_.ravel()], 1).astype(np.int32)
+    rays = synth.Rays(c2w[None], intr[None], np.array([0, W * W], np.int32), pix)
+    opts = synth.Opts(step_vox=0.5, max_samples=100_000, t_near=0.0, t_stop=synth.f32(1e-6),
+                      color_act=synth.COLOR_SIGMOID, depth_loss=synth.DEPTH_L1, lambda_depth=1.0)
+    rgb, depth, _, _ = oracle.render(g, rays, opts)
+    tgt_rgb = (rgb + 0.05 * rng.normal(size=rgb.shape)).astype(np.float32)
+    tgt_depth = np.where(depth > 0, 1.02 * depth, 0.0).astype(np.float32)   # misses: invalid
+    tg = synth.Targets(tgt_rgb, tgt_depth, np.array([1.0 / (W * W)], np.float32))
+    return synth.Workload(f"lattice{reso}", g, rays, tg, opts)
+
+
+@pytest.mark.parametrize("reso", [(2, 2, 2), (2, 3, 70), (70, 2, 3)])
+def test_minimum_and_thin_lattices(reso):
+    """Degenerate lattice sizes through every grid entry point: the fused
+    step in one and two launches, TV, growth and pruning."""
+    pxm = _dev()
+    wl = _small_lattice_workload(reso, 81 + sum(reso))
+    ref = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
+    hit = ref["depth"] > 0
+    assert hit.sum() > 20, "the camera must see the box"
+    _fused_check(wl, 3, f"lattice {reso}", ref, block=64, variant=1)
+    _fused_check(wl, 3, f"lattice {reso} two launches", ref, block=64, variant=2)
+    g = pxm.grid_to_device(wl.grid)
+    _, tv_ref = oracle.tv(wl.grid, 1e-2, 1e-3, 1e-6)
+    tv = pxm.tv_grad(g, 1e-2, 1e-3, 1e-6)
+    torch.cuda.synchronize()
+    assert_r28(np_(tv), tv_ref, TAU_GRAD, f"lattice {reso} tv")
+    up_ref = oracle.grid_upsample(wl.grid)
+    up = pxm.grid_upsample(g)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np_(up.link), up_ref.link)
+    assert np.array_equal(np_(up.data), up_ref.data)
+    tau = float(np.median(wl.grid.data[:, 0]))
+    pr_ref = oracle.grid_prune(wl.grid, np.float32(tau))
+    pr = pxm.grid_prune(g, tau)
+    np.testing.assert_array_equal(np_(pr.link), pr_ref.link)
+    assert np.array_equal(np_(pr.data), pr_ref.data)
