@@ -651,3 +651,17 @@ def test_minimum_and_thin_lattices(reso):
     pr = pxm.grid_prune(g, tau)
     np.testing.assert_array_equal(np_(pr.link), pr_ref.link)
     assert np.array_equal(np_(pr.data), pr_ref.data)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_fused_sample_cap_near_plane_and_early_stop(c1, variant):
+    """A cap that cuts most rays (20 kept positions), a near plane inside the
+    grid and early termination: the backward replays exactly the samples the
+    forward kept, in one launch and in two."""
+    wl, _ = c1
+    opts = dataclasses.replace(wl.opts, max_samples=20, t_near=synth.f32(2.4),
+                               t_stop=synth.f32(0.05))
+    wlc = wl.replace(opts=opts)
+    ref = oracle.fused(wlc.grid, wlc.rays, wlc.targets, wlc.opts)
+    assert (ref["nsamp"] == 20).sum() > 100, "the cap must bind on many rays"
+    _fused_check(wlc, 3, f"c1 capped v{variant}", ref, block=64, variant=variant)
