@@ -665,3 +665,14 @@ def test_fused_sample_cap_near_plane_and_early_stop(c1, variant):
     ref = oracle.fused(wlc.grid, wlc.rays, wlc.targets, wlc.opts)
     assert (ref["nsamp"] == 20).sum() > 100, "the cap must bind on many rays"
     _fused_check(wlc, 3, f"c1 capped v{variant}", ref, block=64, variant=variant)
+
+
+@pytest.mark.parametrize("act,depth_loss", [(synth.COLOR_SIGMOID, synth.DEPTH_L2),
+                                            (synth.COLOR_IDENTITY, synth.DEPTH_L1)])
+def test_fused_colour_activations_and_depth_norms(c1, act, depth_loss):
+    """The fused step for the other colour activations (c1 itself uses the
+    shifted ReLU) and both depth norms of the loss."""
+    wl, _ = c1
+    wla = wl.replace(opts=dataclasses.replace(wl.opts, color_act=act, depth_loss=depth_loss))
+    ref = oracle.fused(wla.grid, wla.rays, wla.targets, wla.opts)
+    _fused_check(wla, 3, f"c1 act {act} depth {depth_loss}", ref)
