@@ -200,10 +200,11 @@ def test_fused_c1_launch_shapes(c1, block, variant):
     _fused_check(wl, 3, f"c1 b{block} v{variant}", ref, block, variant)
 
 
-def test_fused_c1_grid_only_and_pose_only(c1):
+@pytest.mark.parametrize("block,variant", [(256, 0), (64, 2)])
+def test_fused_c1_grid_only_and_pose_only(c1, block, variant):
     wl, ref = c1
-    _fused_check(wl, 1, "c1 grid", ref)
-    _fused_check(wl, 2, "c1 pose", ref)
+    _fused_check(wl, 1, f"c1 grid {block}/{variant}", ref, block, variant)
+    _fused_check(wl, 2, f"c1 pose {block}/{variant}", ref, block, variant)
 
 
 def test_fused_all_targets_invalid(c1):
@@ -243,6 +244,8 @@ def test_fused_view_direction_pose_term(c1):
     assert r28_ratio(plain["grad_pose"][:, 3:], ref["grad_pose"][:, 3:]) > 10 * TAU_GRAD
     _fused_check(wlv, 3, "c1 grid+pose viewdir", ref)
     _fused_check(wlv, 2, "c1 pose viewdir", ref)
+    _fused_check(wlv, 3, "c1 grid+pose viewdir two launches", ref, 64, 2)
+    _fused_check(wlv, 2, "c1 pose viewdir two launches", ref, 64, 2)
 
 
 def test_fused_c3_tracking_view_direction(c3):
