@@ -202,9 +202,11 @@ def test_fused_c1_launch_shapes(c1, block, variant):
 
 @pytest.mark.parametrize("block,variant", [(256, 0), (64, 2)])
 def test_fused_c1_grid_only_and_pose_only(c1, block, variant):
+    """Grid gradient only, pose gradient only, and neither (forward and loss)."""
     wl, ref = c1
     _fused_check(wl, 1, f"c1 grid {block}/{variant}", ref, block, variant)
     _fused_check(wl, 2, f"c1 pose {block}/{variant}", ref, block, variant)
+    _fused_check(wl, 0, f"c1 loss only {block}/{variant}", ref, block, variant)
 
 
 def test_fused_all_targets_invalid(c1):
