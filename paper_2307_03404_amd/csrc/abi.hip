@@ -11,8 +11,13 @@
 namespace {
 
 thread_local char g_err[512] = "";
-std::atomic<int> g_block{256};
-std::atomic<int> g_variant{0};
+// Launch tuning of pxm_render_fused: rays per workgroup in the low 16 bits,
+// variant above them, in ONE atomic word so that a reader never sees the
+// block of one pxm_set_tuning call with the variant of another.
+constexpr int32_t TUNE_DEFAULT = 256;
+std::atomic<int32_t> g_tuning{TUNE_DEFAULT};
+inline int32_t tune_block(int32_t t) { return t & 0xffff; }
+inline int32_t tune_variant(int32_t t) { return t >> 16; }
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -149,14 +154,14 @@ int pxm_set_tuning(int32_t block, int32_t variant) {
     if (block != 64 && block != 128 && block != 256)
         return fail(PXM_INVALID_ARGUMENT, "block = %d not in {64,128,256}", block);
     if (variant < 0 || variant > 2) return fail(PXM_INVALID_ARGUMENT, "variant = %d not in {0,1,2}", variant);
-    g_block.store(block);
-    g_variant.store(variant);
+    g_tuning.store(block | (variant << 16));
     return PXM_OK;
 }
 
 void pxm_get_tuning(int32_t* block, int32_t* variant) {
-    if (block) *block = g_block.load();
-    if (variant) *variant = g_variant.load();
+    const int32_t t = g_tuning.load();
+    if (block) *block = tune_block(t);
+    if (variant) *variant = tune_variant(t);
 }
 
 int pxm_render_forward(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
@@ -260,7 +265,8 @@ int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts*
     if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(PXM_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
     if (ws_bytes < need) return fail(PXM_WORKSPACE_TOO_SMALL, "workspace %zu < %zu bytes", ws_bytes, need);
     if (rays->n_rays == 0) return PXM_OK;
-    const int block = g_block.load(), variant = g_variant.load();
+    const int32_t tune = g_tuning.load();
+    const int block = tune_block(tune), variant = tune_variant(tune);
     return launched(pxm::launch_fused(kgrid(grid), krays(rays), kopts(opts), tgt_rgb, tgt_depth,
                                       frame_weight, want, rgb, depth, loss, grad_data, grad_pose,
                                       stats, reinterpret_cast<unsigned*>(ws), block, variant,

@@ -12,6 +12,8 @@
 // stored per sample), and scatter or reduce the gradients.  Gauss-Newton
 // (Sec. 5.3): per-ray pose Jacobians of the four outputs from the same march,
 // reduced to per-frame normal equations.
+#include <atomic>
+
 #include "internal.hpp"
 #include "scatter.hpp"
 
@@ -813,19 +815,21 @@ static int device_cus() {
 
 // Persistent grid: as many workgroups as the device holds at once (from the
 // kernel's register and LDS use), never more than there are tiles.
+// The per-CU figure is cached per kernel and block size; concurrent callers
+// may both compute it, and they store the same value.
 template <bool GRID, bool POSE, bool VIEW, int PH>
 static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
-    static int per_cu[4] = {0, 0, 0, 0};                  // by block 64/128/256/512
+    static std::atomic<int> per_cu[4];                    // by block 64/128/256/512, 0 = unknown
     const int slot = block == 64 ? 0 : block == 128 ? 1 : block == 256 ? 2 : 3;
-    if (per_cu[slot] <= 0) {
-        int n = 0;
+    int n = per_cu[slot].load(std::memory_order_relaxed);
+    if (n <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW, PH>, block, lds)
                 != hipSuccess || n <= 0)
             n = 1;
-        per_cu[slot] = n;
+        per_cu[slot].store(n, std::memory_order_relaxed);
     }
-    static int cus = device_cus();
-    const int64_t cap = (int64_t)cus * per_cu[slot];
+    static const int cus = device_cus();
+    const int64_t cap = (int64_t)cus * n;
     return (unsigned)(tiles < cap ? tiles : cap);
 }
 
@@ -870,7 +874,7 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
     if (want & 1) {
         // the grid scatter needs WAVE_LDS_FLOATS of LDS per wave: shrink the
         // workgroup if the device cannot give this many waves' worth
-        static size_t max_lds = device_lds();
+        static const size_t max_lds = device_lds();
         while (block > WAVE && (size_t)(block / WAVE) * WAVE_LDS_FLOATS * sizeof(float) > max_lds)
             block /= 2;
     }

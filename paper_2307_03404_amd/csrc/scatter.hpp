@@ -40,10 +40,22 @@ struct WaveStage {
     uint32_t* marks;    // [MARK_WORDS][WAVE] each lane's work-position mask (fused kernel)
 };
 
+// Must be reached by every lane of the wave, before its first scatter.  The
+// MFMA B operand reads rows 0..31 of each half of the staging block, but a
+// gradient row has only REC = 28 fields: rows 28..31 are never staged, so
+// they are zeroed here once (their products land in output columns that
+// are discarded, and the matrix cores then never see undefined LDS).
 __device__ __forceinline__ WaveStage wave_stage(float* smem) {
     const int w = threadIdx.x / WAVE;
     float* sb = smem + (size_t)w * WAVE_LDS_FLOATS;
     float* sw = sb + STAGE_FLOATS;                        // 2112 floats in: 16-byte aligned
+    const int lane = (int)(threadIdx.x % WAVE);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = lane * 4 + q;                       // 2 halves x 4 rows x 32 columns
+        const int h = i >> 7, row = REC + ((i >> 5) & 3), c = i & 31;
+        sb[((h << 5) + row) * STAGE_LD + c] = 0.f;
+    }
     return WaveStage{sb, sw, reinterpret_cast<uint32_t*>(sw + WAVE * 8)};
 }
 
@@ -56,6 +68,8 @@ __device__ __forceinline__ int stage_at(int i, int ray_lane) {
 // ---------------------------------------------------------------------------
 // the scatter
 // ---------------------------------------------------------------------------
+
+static_assert(REC + 4 == 32, "the staging rows beyond the record are the last four of 32");
 
 // A pass whose groups cover at most this many lanes is summed lane by lane
 // (broadcast of each member's weights and gradient row from LDS) instead of
