@@ -26,19 +26,27 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# A test that plants a mistake in a copy of oracle.c (to show that the pins
+# catch it) points this variable at the library built from that copy.
+_LIB_OVERRIDE = os.environ.get("PXM_ORACLE_LIB")
 _lib = None
 
 NREC = 28
 
 
-def build(verbose=False) -> str:
-    """Compile the oracle with gcc (plain IEEE double, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-o", _LIB_PATH, os.path.join(_HERE, "oracle.c"), "-lm"]
+GCC_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off"]
+
+
+def build(verbose=False, src=None, out=None, extra=()) -> str:
+    """Compile the oracle with gcc (plain IEEE double, no FMA contraction).
+    `src`, `out` and `extra` flags serve the tests that build instrumented or
+    deliberately broken copies; the default builds oracle.c in place."""
+    out = out or _LIB_PATH
+    cmd = ["gcc", *GCC_FLAGS, *extra, "-o", out, src or os.path.join(_HERE, "oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return _LIB_PATH
+    return out
 
 
 def _load():
@@ -46,9 +54,12 @@ def _load():
     if _lib is not None:
         return _lib
     src = os.path.join(_HERE, "oracle.c")
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
-        build()
-    lib = C.CDLL(_LIB_PATH)
+    if _LIB_OVERRIDE:
+        lib = C.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+            build()
+        lib = C.CDLL(_LIB_PATH)
     P = C.c_void_p
     i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
     lib.orc_render.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64, i32,
