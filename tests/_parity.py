@@ -33,38 +33,69 @@ def assert_r28(x, ref, tau, what):
     return ratio
 
 
-def align_depth_decisions(wl, ref, gpu_depth):
-    """The L1 depth loss (Eq. 5 with the L1 norm of Sec. 6.1) has a kink at a
-    zero residual, where its derivative is a sign.  When the residual lies
-    below FP32 resolution the kernel (FP32) and the oracle (FP64) can take
-    opposite signs; both are valid subgradients.  The decision is taken in the
-    kernel's precision: for those rays the oracle's backward is re-run with
-    the sign of (kernel z-depth - target) computed in FP32 from the kernel's
-    own depth output.  Returns (ref, number of rays re-decided)."""
-    import oracle
+# At most this fraction of a workload's valid rays may have their target
+# depth moved off the L1 kink (a residual inside the band below is a
+# measure-zero event for continuous noise: ~0.3 % of rays at 1 cm noise).
+KINK_MAX_FRACTION = 0.01
+
+
+def kink_band(depth_ref):
+    """Residuals |z - D| inside this band could take either sign in the
+    kernel: the forward is only required to match within TAU_FWD
+    (relative, with an RMS floor), so a sign there is not decided by the
+    method but by FP32 rounding."""
+    depth_ref = np.asarray(depth_ref, np.float64)
+    rms = float(np.sqrt(np.mean(depth_ref * depth_ref))) if depth_ref.size else 0.0
+    return 2.0 * TAU_FWD * np.maximum(np.abs(depth_ref), rms)
+
+
+def kink_free_targets(wl, depth_ref):
+    """The L1 depth loss (Eq. 5 with the L1 norm of Sec. 6.1) has a kink at
+    a zero residual, where its derivative is a sign.  Targets whose residual
+    against the ORACLE's z-depth lies inside kink_band are moved to twice
+    the band on the side of their residual (a zero residual goes to the
+    positive side), so both the FP64 oracle and the FP32 kernel take the
+    same, method-determined decision.  Only oracle values enter: no kernel
+    output is used.  Returns (workload, number of targets moved)."""
     from paper_2307_03404_amd import synth
     if wl.opts.depth_loss != synth.DEPTH_L1:
-        return ref, 0
+        return wl, 0
+    z = np.asarray(depth_ref, np.float64)
     D32 = np.asarray(wl.targets.depth, np.float32)
-    valid = np.isfinite(D32) & (D32 > 0)
     with np.errstate(invalid="ignore"):
-        s_gpu = np.sign(np.asarray(gpu_depth, np.float32) - D32)
-        s_ref = np.sign(ref["depth"] - D32.astype(np.float64))
-    amb = valid & (s_gpu != s_ref)
-    if not amb.any():
-        return ref, 0
-    resid = np.abs(ref["depth"][amb] - D32[amb].astype(np.float64))
-    assert np.all(resid <= 1e-5 * np.abs(D32[amb])), "sign disagreement on a resolvable residual"
-    off = wl.rays.frame_offsets
-    fid = np.searchsorted(off, np.arange(wl.rays.n_rays), side="right") - 1
-    g_depth = ref["g_depth"].copy()
-    g_depth[amb] = (float(np.float32(wl.opts.lambda_depth)) * wl.targets.frame_weight[fid[amb]]
-                    * s_gpu[amb])
-    gd, gp = oracle.backward(wl.grid, wl.rays, wl.opts, ref["g_rgb"], g_depth,
-                             ref["grad_data"] is not None, ref["grad_pose"] is not None)
-    out = dict(ref)
-    out.update(g_depth=g_depth, grad_data=gd, grad_pose=gp)
-    return out, int(amb.sum())
+        valid = np.isfinite(D32) & (D32 > 0)
+    band = kink_band(z)
+    near = valid & (np.abs(z - D32.astype(np.float64)) <= band)
+    n = int(near.sum())
+    if n == 0:
+        return wl, 0
+    assert n <= max(5, KINK_MAX_FRACTION * int(valid.sum())), \
+        f"{n} of {int(valid.sum())} targets sit on the L1 kink"
+    sgn = np.sign(z[near] - D32[near].astype(np.float64))
+    sgn[sgn == 0] = 1.0
+    D = D32.copy()
+    D[near] = (z[near] - sgn * 2.0 * band[near]).astype(np.float32)
+    moved = np.abs(z[near] - D[near].astype(np.float64))
+    assert np.all(moved > band[near]) and np.all(D[near] > 0)
+    import dataclasses
+    tg = dataclasses.replace(wl.targets, depth=D)
+    return wl.replace(targets=tg), n
+
+
+def reference(wl, want_grid=True, want_pose=True, quiet=False):
+    """The FP64 oracle's forward, loss and backward of one batch, with the
+    targets first moved off the L1 kink (kink_free_targets).  Returns the
+    workload to feed the GPU (its targets possibly moved) and the reference."""
+    import oracle
+    rgb, depth, nsamp, stats = oracle.render(wl.grid, wl.rays, wl.opts)
+    wl, n = kink_free_targets(wl, depth)
+    if n and not quiet:
+        print(f"{wl.name}: {n} target depth(s) moved off the L1 kink "
+              f"(bound {KINK_MAX_FRACTION:.0%} of valid rays)", flush=True)
+    L, g_rgb, g_depth = oracle.loss(wl.rays, rgb, depth, wl.targets, wl.opts)
+    gd, gp = oracle.backward(wl.grid, wl.rays, wl.opts, g_rgb, g_depth, want_grid, want_pose)
+    return wl, dict(rgb=rgb, depth=depth, nsamp=nsamp, stats=stats, loss=L, g_rgb=g_rgb,
+                    g_depth=g_depth, grad_data=gd, grad_pose=gp, kink_moved=n)
 
 
 def assert_pose(gp, ref, tau, what):

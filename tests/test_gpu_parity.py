@@ -8,8 +8,7 @@ import pytest
 
 import oracle
 from paper_2307_03404_amd import synth
-from tests._parity import (TAU_FWD, TAU_GRAD, align_depth_decisions, assert_pose, assert_r28,
-                           r28_ratio)
+from tests._parity import TAU_FWD, TAU_GRAD, assert_pose, assert_r28, r28_ratio, reference
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +38,7 @@ def np_(t):
 
 @pytest.fixture(scope="module")
 def c1():
-    wl = synth.config1()
-    ref = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
-    return wl, ref
+    return reference(synth.config1())
 
 
 # ------------------------------------------------------------------ forward
@@ -54,7 +51,26 @@ def test_forward_c1(c1):
     torch.cuda.synchronize()
     assert_r28(np_(rgb), ref["rgb"], TAU_FWD, "rgb")
     assert_r28(np_(depth), ref["depth"], TAU_FWD, "depth")
-    assert (np_(nsamp) != ref["nsamp"]).mean() < 1e-3
+    check_nsamp(wl, np_(nsamp), ref["nsamp"])
+
+
+def check_nsamp(wl, got, want, max_fraction=1e-3):
+    """Kept sample counts agree, except on rays whose early-termination test
+    T_{i+1} < t_stop (Sec. 4 reading: stop once T falls below t_stop) is
+    decided by rounding: there the oracle's transmittance at the earlier of
+    the two stopping points must lie within 1e-4 (relative) of t_stop."""
+    bad = np.flatnonzero(got != want)
+    assert bad.size <= max(2, max_fraction * got.size), f"{bad.size} rays disagree on nsamp"
+    off = wl.rays.frame_offsets
+    for r in bad:
+        f = int(np.searchsorted(off, r, side="right") - 1)
+        o, d, _ = oracle.ray(wl.rays.c2w[f], wl.rays.intr[f], *wl.rays.pix[r])
+        tr = oracle.trace(wl.grid, o, d, wl.opts)
+        m = int(min(got[r], want[r]))
+        T = tr["T"][m]
+        assert abs(T / wl.opts.t_stop - 1.0) < 1e-4, \
+            f"ray {r}: nsamp {got[r]} vs {want[r]} with T = {T:.6e}, t_stop {wl.opts.t_stop:.6e}"
+    return bad.size
 
 
 def test_forward_cap_and_tail_and_misses(c1):
@@ -141,9 +157,10 @@ def test_backward_pose_c1(c1, viewdir):
 # ------------------------------------------------------------------ fused
 
 def _fused_check(wl, want, what, ref=None, block=None, variant=None):
+    """`ref` comes from reference(wl), with `wl` the workload it returned."""
     pxm = _dev()
     if ref is None:
-        ref = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
+        wl, ref = reference(wl)
     g, r, t = to_dev(wl)
     n, F = wl.rays.n_rays, wl.rays.n_frames
     rgb = torch.empty(n, 3, device="cuda")
@@ -167,10 +184,7 @@ def _fused_check(wl, want, what, ref=None, block=None, variant=None):
             assert_r28(np_(rgb), ref["rgb"], TAU_FWD, what + " rgb")
             assert_r28(np_(depth), ref["depth"], TAU_FWD, what + " depth")
             assert_r28(np_(loss), ref["loss"], TAU_FWD, what + " loss")
-            gref, nflip = align_depth_decisions(wl, ref, np_(depth))
-            if nflip:
-                print(f"{what}: {nflip} ray(s) with an FP32-resolution depth residual "
-                      "take the kernel's L1 sign", flush=True)
+            gref = ref
             if want & pxm.WANT_GRID:
                 assert_r28(np_(gd)[:, 0], gref["grad_data"][:, 0], TAU_GRAD, what + " grad density")
                 assert_r28(np_(gd)[:, 1:], gref["grad_data"][:, 1:], TAU_GRAD, what + " grad sh")
@@ -238,8 +252,7 @@ def test_fused_view_direction_pose_term(c1):
     """The exact view-direction pose term (PXM_FLAG_POSE_VIEWDIR) in the fused
     kernel, grid + pose and pose only, against the oracle with the same flag."""
     wl, _ = c1
-    wlv = wl.replace(opts=dataclasses.replace(wl.opts, flags=synth.FLAG_POSE_VIEWDIR))
-    ref = oracle.fused(wlv.grid, wlv.rays, wlv.targets, wlv.opts)
+    wlv, ref = reference(wl.replace(opts=dataclasses.replace(wl.opts, flags=synth.FLAG_POSE_VIEWDIR)))
     plain = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
     # the term moves the rotation gradient well beyond the tolerance: a kernel
     # that ignored the flag would fail
@@ -252,8 +265,8 @@ def test_fused_view_direction_pose_term(c1):
 
 def test_fused_c3_tracking_view_direction(c3):
     sub = synth.subset_rays(c3, 40000, seed=12)
-    subv = sub.replace(opts=dataclasses.replace(sub.opts, flags=synth.FLAG_POSE_VIEWDIR))
-    ref = oracle.fused(subv.grid, subv.rays, subv.targets, subv.opts, want_grid=False)
+    subv, ref = reference(sub.replace(opts=dataclasses.replace(sub.opts, flags=synth.FLAG_POSE_VIEWDIR)),
+                          want_grid=False)
     plain = oracle.fused(sub.grid, sub.rays, sub.targets, sub.opts, want_grid=False)
     assert r28_ratio(plain["grad_pose"][:, 3:], ref["grad_pose"][:, 3:]) > 10 * TAU_GRAD
     _fused_check(subv, 2, "c3 pose viewdir", ref)
@@ -334,8 +347,8 @@ def test_fused_c2_tiles_without_occupancy(c2):
     rays = dataclasses.replace(wl.rays, pix=wl.rays.pix[a:b],
                                frame_offsets=np.array([0, b - a], np.int32))
     tg = dataclasses.replace(wl.targets, rgb=wl.targets.rgb[a:b], depth=wl.targets.depth[a:b])
-    sub = wl.replace(rays=rays, targets=tg)
-    ref = oracle.fused(sub.grid, sub.rays, sub.targets, sub.opts)
+    sub, ref = reference(wl.replace(rays=rays, targets=tg))
+    tg = sub.targets
     outs = []
     for occ in (True, False):
         g = pxm.grid_to_device(sub.grid, occupancy=occ)
@@ -350,9 +363,8 @@ def test_fused_c2_tiles_without_occupancy(c2):
                          grad_data=gd, grad_pose=gp, stats=st)
         torch.cuda.synchronize()
         assert_r28(np_(rgb), ref["rgb"], TAU_FWD, f"rgb occ={occ}")
-        gref, _ = align_depth_decisions(sub, ref, np_(depth))
-        assert_r28(np_(gd), gref["grad_data"], TAU_GRAD, f"grad occ={occ}")
-        assert_pose(np_(gp), gref["grad_pose"], TAU_GRAD, f"pose occ={occ}")
+        assert_r28(np_(gd), ref["grad_data"], TAU_GRAD, f"grad occ={occ}")
+        assert_pose(np_(gp), ref["grad_pose"], TAU_GRAD, f"pose occ={occ}")
         outs.append((np_(rgb), np_(st)))
     np.testing.assert_array_equal(outs[0][0], outs[1][0])      # forward bitwise identical
     np.testing.assert_array_equal(outs[0][1], outs[1][1])      # same samples counted
@@ -360,14 +372,15 @@ def test_fused_c2_tiles_without_occupancy(c2):
 
 @pytest.fixture(scope="module")
 def c2_ref(c2):
-    return oracle.fused(c2.grid, c2.rays, c2.targets, c2.opts)
+    return reference(c2)
 
 
 @pytest.mark.parametrize("variant", [1, 2])
-def test_fused_c2_full_frame(c2, c2_ref, variant):
+def test_fused_c2_full_frame(c2_ref, variant):
     """The whole 816,000-ray frame at the bench launch configuration (one
     launch, persistent) and in the two-launch form."""
-    _fused_check(c2, 3, f"c2 full v{variant}", c2_ref, block=64, variant=variant)
+    wl, ref = c2_ref
+    _fused_check(wl, 3, f"c2 full v{variant}", ref, block=64, variant=variant)
 
 
 def test_tv_c2(c2):
@@ -426,8 +439,7 @@ def test_empty_grid_every_entry_point():
     R = wl.grid.reso
     empty = synth.Grid(R, wl.grid.aabb_min, wl.grid.voxel_size,
                        np.full(int(np.prod(R)), -1, np.int32), np.zeros((0, 28), np.float32))
-    wl = wl.replace(grid=empty)
-    ref = oracle.fused(empty, wl.rays, wl.targets, wl.opts)
+    wl, ref = reference(wl.replace(grid=empty))
     g, r, t = to_dev(wl)
     assert g.data.numel() == 0 and int(g.occ.sum()) == 0
     n, F = wl.rays.n_rays, wl.rays.n_frames
@@ -474,8 +486,8 @@ def test_axis_aligned_rays():
     rgb0, depth0, _, _ = oracle.render(grid, rays, synth.Opts(step_vox=0.5, depth_loss=synth.DEPTH_L1))
     tg = synth.Targets((rgb0 + 0.05).astype(np.float32), (depth0 * 1.02 + 0.01).astype(np.float32),
                        synth.frame_weights(depth0 * 1.02 + 0.01, rays.frame_offsets, True))
-    wl = synth.Workload("axis", grid, rays, tg, synth.Opts(step_vox=0.5, depth_loss=synth.DEPTH_L2))
-    ref = oracle.fused(grid, rays, tg, wl.opts)
+    wl, ref = reference(synth.Workload("axis", grid, rays, tg,
+                                       synth.Opts(step_vox=0.5, depth_loss=synth.DEPTH_L2)))
     for occ in (True, False):
         g = pxm.grid_to_device(grid, occupancy=occ)
         r = pxm.rays_to_device(rays)
@@ -527,7 +539,8 @@ def test_fused_long_rays_fall_back_to_scanning():
     assert nsamp[:64].max() > 1100 and nsamp[64:].max() < 1024
     tg = synth.Targets((rgb0 + 0.05).astype(np.float32), (depth0 * 1.01).astype(np.float32),
                        synth.frame_weights(depth0 * 1.01, rays.frame_offsets, True))
-    ref = oracle.fused(grid, rays, tg, opts)
+    wl, ref = reference(synth.Workload("long", grid, rays, tg, opts))
+    tg = wl.targets
     for occ in (True, False):
         g = pxm.grid_to_device(grid, occupancy=occ)
         r = pxm.rays_to_device(rays)
@@ -584,10 +597,12 @@ def test_pose_adam_matches_oracle(c3):
 
 # ------------------------------------------------------------------ autograd
 
-def test_autograd_matches_direct_calls(c1):
+def _autograd_check(wl, ref, what):
+    """Eq. 4, 5, 11 written in torch over the differentiable render (saved
+    state: rgb, depth, nsamp per ray; the backward recomputes the samples),
+    against the oracle's grid and pose gradients of the same loss."""
     pxm = _dev()
     from paper_2307_03404_amd import autograd as AG
-    wl, _ = c1
     g, r, t = to_dev(wl)
     data = g.data.clone().requires_grad_(True)
     xi = torch.zeros(1, 6, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -599,9 +614,21 @@ def test_autograd_matches_direct_calls(c1):
     loss = (ec ** 2).sum() / m + dd.abs().sum() / m
     loss.backward()
     torch.cuda.synchronize()
-    ref = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
-    assert_r28(np_(data.grad), ref["grad_data"], TAU_GRAD, "autograd grid")
-    assert_pose(np_(xi.grad), ref["grad_pose"], TAU_GRAD, "autograd pose")
+    assert_r28(np_(rgb), ref["rgb"], TAU_FWD, what + " rgb")
+    assert_r28(np_(data.grad), ref["grad_data"], TAU_GRAD, what + " grid")
+    assert_pose(np_(xi.grad), ref["grad_pose"], TAU_GRAD, what + " pose")
+
+
+def test_autograd_matches_direct_calls(c1):
+    wl, ref = c1
+    _autograd_check(wl, ref, "autograd c1")
+
+
+def test_autograd_full_frame_c2(c2_ref):
+    """A whole 1200x680 frame (816,000 rays) through the autograd.Function:
+    20 bytes of saved state per ray, recomputation in the backward."""
+    wl, ref = c2_ref
+    _autograd_check(wl, ref, "autograd c2 full frame")
 
 
 def _small_lattice_workload(reso, seed):
@@ -635,8 +662,7 @@ def test_minimum_and_thin_lattices(reso):
     """Degenerate lattice sizes through every grid entry point: the fused
     step in one and two launches, TV, growth and pruning."""
     pxm = _dev()
-    wl = _small_lattice_workload(reso, 81 + sum(reso))
-    ref = oracle.fused(wl.grid, wl.rays, wl.targets, wl.opts)
+    wl, ref = reference(_small_lattice_workload(reso, 81 + sum(reso)))
     hit = ref["depth"] > 0
     assert hit.sum() > 20, "the camera must see the box"
     _fused_check(wl, 3, f"lattice {reso}", ref, block=64, variant=1)
@@ -666,8 +692,7 @@ def test_fused_sample_cap_near_plane_and_early_stop(c1, variant):
     wl, _ = c1
     opts = dataclasses.replace(wl.opts, max_samples=20, t_near=synth.f32(2.4),
                                t_stop=synth.f32(0.05))
-    wlc = wl.replace(opts=opts)
-    ref = oracle.fused(wlc.grid, wlc.rays, wlc.targets, wlc.opts)
+    wlc, ref = reference(wl.replace(opts=opts))
     assert (ref["nsamp"] == 20).sum() > 100, "the cap must bind on many rays"
     _fused_check(wlc, 3, f"c1 capped v{variant}", ref, block=64, variant=variant)
 
@@ -678,6 +703,6 @@ def test_fused_colour_activations_and_depth_norms(c1, act, depth_loss):
     """The fused step for the other colour activations (c1 itself uses the
     shifted ReLU) and both depth norms of the loss."""
     wl, _ = c1
-    wla = wl.replace(opts=dataclasses.replace(wl.opts, color_act=act, depth_loss=depth_loss))
-    ref = oracle.fused(wla.grid, wla.rays, wla.targets, wla.opts)
+    wla, ref = reference(wl.replace(opts=dataclasses.replace(wl.opts, color_act=act,
+                                                             depth_loss=depth_loss)))
     _fused_check(wla, 3, f"c1 act {act} depth {depth_loss}", ref)
