@@ -323,6 +323,30 @@ int pxm_grid_upsample_data(const pxm_grid *grid, const int32_t *link_fine, int64
 int pxm_grid_prune(const pxm_grid *grid, float tau, int32_t *link_out, float *data_out,
                    int64_t *n_out, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Allocation-free form of pxm_render_fused, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, semantics and results as
+ * pxm_render_fused without the workspace: its scratch (the tile-queue
+ * counters, and in the two-launch form the per-ray state) lives in a static
+ * device array of PXM_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds until the process ends.  The call allocates nothing: it clears the
+ * counters with a kernel on `stream`, then launches as pxm_render_fused.
+ *   Limit: under launch variant 2 (see pxm_set_tuning) at most
+ *   PXM_NOALLOC_MAX_SPLIT_RAYS rays, else PXM_UNSUPPORTED; variants 0 and 1
+ *   take any ray count.
+ *   Concurrency: every call on one GPU shares that GPU's array, so calls that
+ *   overlap on one GPU (two streams, two threads) race and give wrong
+ *   results; serialise them on one stream.
+ */
+#define PXM_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define PXM_NOALLOC_MAX_SPLIT_RAYS 182336
+int pxm_render_fused_noalloc(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
+                             const float *tgt_rgb, const float *tgt_depth,
+                             const float *frame_weight, int32_t want, float *rgb, float *depth,
+                             double *loss, float *grad_data, double *grad_pose, int64_t *stats,
+                             void *stream);
+
 /* Workspace bytes pxm_render_fused needs for these arguments and `want`, under
  * any launch tuning: 256 + 184 * (n_rays rounded up to 64). */
 size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 
 #include "../../include/pxm.h"
 #include "internal.hpp"
@@ -398,6 +399,100 @@ int pxm_grid_prune(const pxm_grid* grid, float tau, int32_t* link_out, float* da
     PXM_TRY(check_edit_ws(grid, ws, ws_bytes));
     return launched(pxm::launch_prune(kgrid(grid), tau, link_out, data_out, n_out, ws, (hipStream_t)stream),
                     "grid_prune");
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free fused step: the workspace is a file-scope device array.
+// ---------------------------------------------------------------------------
+
+// One copy per GPU, alive until the process ends.  Host code must never pass
+// `scratch` itself to a kernel (in host code it names a host-side stand-in):
+// its device address is looked up once per device and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[PXM_NOALLOC_SCRATCH_BYTES];
+
+static_assert(pxm::FUSED_WS_BYTES + (size_t)PXM_NOALLOC_MAX_SPLIT_RAYS * pxm::SPLIT_BYTES_PER_RAY
+                  <= (size_t)PXM_NOALLOC_SCRATCH_BYTES
+              && PXM_NOALLOC_MAX_SPLIT_RAYS % 64 == 0
+              && pxm::FUSED_WS_BYTES + ((size_t)PXM_NOALLOC_MAX_SPLIT_RAYS + 64) * pxm::SPLIT_BYTES_PER_RAY
+                  > (size_t)PXM_NOALLOC_SCRATCH_BYTES,
+              "PXM_NOALLOC_MAX_SPLIT_RAYS is the largest ray count whose split state fits the scratch");
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::atomic<void*> g_scratch[MAX_DEVICES];
+std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array, looked up on first use with
+// the device current.
+int scratch_ptr(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PXM_DEVICE_ERROR, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PXM_UNSUPPORTED, "device %d beyond %d", dev, MAX_DEVICES);
+    void* p = g_scratch[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        p = g_scratch[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(PXM_DEVICE_ERROR, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            g_scratch[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return PXM_OK;
+}
+
+// Clears the tile-queue counters with a kernel (not a memset node, so the
+// call stays capturable).
+__global__ void k_clear_counters(unsigned* w, int n) {
+    const int i = (int)threadIdx.x;
+    if (i < n) w[i] = 0u;
+}
+
+}  // namespace
+
+int pxm_render_fused_noalloc(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
+                             const float* tgt_rgb, const float* tgt_depth, const float* frame_weight,
+                             int32_t want, float* rgb, float* depth, double* loss, float* grad_data,
+                             double* grad_pose, int64_t* stats, void* stream) {
+    PXM_TRY(check_grid(grid));
+    PXM_TRY(check_rays(rays));
+    PXM_TRY(check_opts(opts));
+    if (want & ~(PXM_WANT_GRID | PXM_WANT_POSE | PXM_WANT_STATS))
+        return fail(PXM_INVALID_ARGUMENT, "unknown want bits 0x%x", want);
+    if (rays->n_rays > 0 && (!tgt_rgb || !tgt_depth || !frame_weight))
+        return fail(PXM_INVALID_ARGUMENT, "targets / frame_weight is NULL");
+    if ((want & PXM_WANT_GRID) && !grad_data && grid->n_alloc > 0)
+        return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
+    if ((want & PXM_WANT_POSE) && !grad_pose) return fail(PXM_INVALID_ARGUMENT, "grad_pose is NULL");
+    if ((want & PXM_WANT_STATS) && !stats) return fail(PXM_INVALID_ARGUMENT, "stats is NULL");
+    const int32_t tune = g_tuning.load();
+    const int block = tune_block(tune), variant = tune_variant(tune);
+    // the two-launch form keeps per-ray state in the scratch; the others only
+    // the queue counters
+    const size_t need = variant == 2 ? pxm::fused_workspace_bytes(rays->n_rays) : pxm::FUSED_WS_BYTES;
+    if (need > (size_t)PXM_NOALLOC_SCRATCH_BYTES)
+        return fail(PXM_UNSUPPORTED,
+                    "%lld rays need %zu bytes of scratch in the two-launch form, above the %zu-byte "
+                    "static scratch (at most %lld rays; use pxm_render_fused with a workspace, or "
+                    "launch variant 0 or 1)",
+                    (long long)rays->n_rays, need, (size_t)PXM_NOALLOC_SCRATCH_BYTES,
+                    (long long)PXM_NOALLOC_MAX_SPLIT_RAYS);
+    if (rays->n_rays == 0) return PXM_OK;
+    void* ws = nullptr;
+    PXM_TRY(scratch_ptr(&ws));
+    const hipStream_t st = (hipStream_t)stream;
+    unsigned* counters = reinterpret_cast<unsigned*>(ws);
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, st, counters,
+                       (int)(pxm::FUSED_WS_BYTES / sizeof(unsigned)));
+    PXM_TRY(launched(hipGetLastError(), "render_fused_noalloc (clear)"));
+    return launched(pxm::launch_fused(kgrid(grid), krays(rays), kopts(opts), tgt_rgb, tgt_depth,
+                                      frame_weight, want, rgb, depth, loss, grad_data, grad_pose,
+                                      stats, counters, block, variant, st),
+                    "render_fused_noalloc");
 }
 
 }  // extern "C"

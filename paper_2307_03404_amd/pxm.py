@@ -54,8 +54,8 @@ class _Opts(C.Structure):
 _lib = None
 _lock = threading.Lock()
 EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
-           "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_grid_rmsprop",
-           "pxm_render_gn", "pxm_pose_gn",
+           "pxm_tv_grad", "pxm_render_fused", "pxm_render_fused_noalloc", "pxm_pose_adam",
+           "pxm_grid_rmsprop", "pxm_render_gn", "pxm_pose_gn",
            "pxm_grid_edit_workspace_bytes", "pxm_grid_upsample_link", "pxm_grid_upsample_data",
            "pxm_grid_prune",
            "pxm_workspace_bytes",
@@ -83,6 +83,7 @@ def lib():
         L.pxm_render_backward_pose.argtypes = [G, R, O, P, P, P, P, P, P, P]
         L.pxm_tv_grad.argtypes = [G, f32, f32, f32, P, P]
         L.pxm_render_fused.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P, sz, P]
+        L.pxm_render_fused_noalloc.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P]
         L.pxm_pose_adam.argtypes = [i32, P, P, P, f32, f32, f32, f32, P]
         L.pxm_grid_rmsprop.argtypes = [i64, P, P, P, f32, f32, f32, f32, P]
         L.pxm_render_gn.argtypes = [G, R, O, P, P, P, P, P]
@@ -105,7 +106,8 @@ def lib():
         L.pxm_status_string.restype = C.c_char_p
         L.pxm_last_error.restype = C.c_char_p
         for name in ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
-                     "pxm_tv_grad", "pxm_render_fused", "pxm_pose_adam", "pxm_set_tuning",
+                     "pxm_tv_grad", "pxm_render_fused", "pxm_render_fused_noalloc",
+                     "pxm_pose_adam", "pxm_set_tuning",
                      "pxm_grid_upsample_link", "pxm_grid_upsample_data", "pxm_grid_prune"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -348,6 +350,36 @@ def render_fused(grid, rays, opts, tgt_rgb, tgt_depth, frame_weight, want, rgb=N
         C.byref(g), C.byref(r), C.byref(o), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(frame_weight),
         int(want), _ptr(rgb), _ptr(depth), _ptr(loss), _ptr(grad_data), _ptr(grad_pose),
         _ptr(stats), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return dict(rgb=rgb, depth=depth, loss=loss, grad_data=grad_data, grad_pose=grad_pose,
+                stats=stats)
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+NOALLOC_MAX_SPLIT_RAYS = 182336
+
+
+def render_fused_noalloc(grid, rays, opts, tgt_rgb, tgt_depth, frame_weight, want, rgb=None,
+                         depth=None, loss=None, grad_data=None, grad_pose=None, stats=None,
+                         stream=None):
+    """render_fused without a workspace: the library's static per-GPU scratch
+    serves instead (calls that overlap on one GPU race).  Raises PxmError
+    (unsupported) above NOALLOC_MAX_SPLIT_RAYS rays under launch variant 2."""
+    n, F = rays.n_rays, rays.n_frames
+    _need(tgt_rgb, "tgt_rgb", torch.float32, (n, 3))
+    _need(tgt_depth, "tgt_depth", torch.float32, (n,))
+    _need(frame_weight, "frame_weight", torch.float32, (F,))
+    for t, name, dt, shp in ((rgb, "rgb", torch.float32, (n, 3)), (depth, "depth", torch.float32, (n,)),
+                             (loss, "loss", torch.float64, (F,)),
+                             (grad_data, "grad_data", torch.float32, tuple(grid.data.shape)),
+                             (grad_pose, "grad_pose", torch.float64, (F, 6)),
+                             (stats, "stats", torch.int64, (4,))):
+        if t is not None:
+            _need(t, name, dt, shp)
+    g, r, o = grid.struct(), rays.struct(), opts_struct(opts)
+    _check("render_fused_noalloc", lib().pxm_render_fused_noalloc(
+        C.byref(g), C.byref(r), C.byref(o), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(frame_weight),
+        int(want), _ptr(rgb), _ptr(depth), _ptr(loss), _ptr(grad_data), _ptr(grad_pose),
+        _ptr(stats), _stream(stream)))
     return dict(rgb=rgb, depth=depth, loss=loss, grad_data=grad_data, grad_pose=grad_pose,
                 stats=stats)
 

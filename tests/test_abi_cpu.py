@@ -226,3 +226,37 @@ def test_upload_helpers_build_descriptors():
     assert r.n_rays == 10 and r.n_frames == 1 and r.frame_offsets.tolist() == [0, 10]
     with pytest.raises(ValueError):
         r.struct()
+
+
+def test_noalloc_fused_argument_checks_and_size_limit():
+    """The allocation-free fused step checks its arguments like
+    pxm_render_fused, and refuses, on the host, a two-launch call whose
+    per-ray state would not fit its static scratch."""
+    L = pxm.lib()
+    g, r, o = good_grid(), good_rays(), good_opts()
+    args = [C.byref(g), C.byref(r), C.byref(o)]
+    assert L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 8, None, None, None, None, None,
+                                      None, None) == 1
+    assert L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 1, None, None, None, None, None,
+                                      None, None) == 1
+    assert L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 2, None, None, None, None, None,
+                                      None, None) == 1
+    assert L.pxm_render_fused_noalloc(*args, None, FAKE, FAKE, 0, None, None, None, None, None,
+                                      None, None) == 1
+    old = (C.c_int32(), C.c_int32())
+    L.pxm_get_tuning(C.byref(old[0]), C.byref(old[1]))
+    try:
+        assert L.pxm_set_tuning(64, 2) == 0
+        big = good_rays(pxm.NOALLOC_MAX_SPLIT_RAYS + 1)
+        st = L.pxm_render_fused_noalloc(C.byref(g), C.byref(big), C.byref(o), FAKE, FAKE, FAKE, 3,
+                                        None, None, None, FAKE, FAKE, None, None)
+        assert st == 2 and b"static scratch" in L.pxm_last_error()
+        zero = good_rays(0)
+        assert L.pxm_render_fused_noalloc(C.byref(g), C.byref(zero), C.byref(o), FAKE, FAKE, FAKE,
+                                          3, None, None, None, FAKE, FAKE, None, None) == 0
+    finally:
+        L.pxm_set_tuning(old[0].value, old[1].value)
+    # the limit in the binding is the header's
+    text = open(HEADER).read()
+    assert f"#define PXM_NOALLOC_MAX_SPLIT_RAYS {pxm.NOALLOC_MAX_SPLIT_RAYS}" in text
+    assert pxm.NOALLOC_SCRATCH_BYTES == 32 << 20 and "(32u << 20)" in text
