@@ -31,7 +31,17 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _LIB_OVERRIDE = os.environ.get("PXM_ORACLE_LIB")
 _lib = None
 
-NREC = 28
+NREC = 28   # floats per record at SH degree 2 (the paper's nine coefficients per channel)
+
+
+def record_floats(deg: int) -> int:
+    """Floats per record of SH degree deg: 4, 16 (13 used) or 28."""
+    return {0: 4, 1: 16, 2: 28}[int(deg)]
+
+
+def used_fields(deg: int) -> int:
+    """Density plus (deg+1)^2 SH coefficients for each of three channels."""
+    return 1 + 3 * (int(deg) + 1) ** 2
 
 
 GCC_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off"]
@@ -62,22 +72,23 @@ def _load():
         lib = C.CDLL(_LIB_PATH)
     P = C.c_void_p
     i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
-    lib.orc_render.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64, i32,
-                               P, P, P, P]
+    lib.orc_render.argtypes = [P, P, f64, P, P, i32, i32, P, P, P, P, i64, f64, i32, f64, f64,
+                               i32, P, P, P, P]
     lib.orc_render.restype = None
-    lib.orc_backward.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64, i32,
-                                 i32, P, P, P, P]
+    lib.orc_backward.argtypes = [P, P, f64, P, P, i32, i32, P, P, P, P, i64, f64, i32, f64, f64,
+                                 i32, i32, P, P, P, P]
     lib.orc_backward.restype = None
-    lib.orc_pose_jacobian.argtypes = [P, P, f64, P, P, i32, P, P, P, P, i64, f64, i32, f64, f64,
-                                      i32, i32, P]
+    lib.orc_pose_jacobian.argtypes = [P, P, f64, P, P, i32, i32, P, P, P, P, i64, f64, i32, f64,
+                                      f64, i32, i32, P]
     lib.orc_pose_jacobian.restype = None
     lib.orc_loss.argtypes = [i32, P, P, P, P, P, P, i32, f64, P, P, P]
     lib.orc_loss.restype = None
-    lib.orc_tv.argtypes = [P, P, P, f64, f64, f64, P]
+    lib.orc_tv.argtypes = [P, P, P, i32, f64, f64, f64, P]
     lib.orc_tv.restype = f64
-    lib.orc_trace.argtypes = [P, P, f64, P, P, P, P, f64, i32, f64, f64, i32, i32, P, P, P, P, P, P]
+    lib.orc_trace.argtypes = [P, P, f64, P, P, i32, P, P, f64, i32, f64, f64, i32, i32, P, P, P, P,
+                              P, P]
     lib.orc_trace.restype = C.c_int
-    lib.orc_interp.argtypes = [P, P, f64, P, P, P, P, P]
+    lib.orc_interp.argtypes = [P, P, f64, P, P, i32, P, P, P]
     lib.orc_interp.restype = None
     lib.orc_sh_basis.argtypes = [P, P]
     lib.orc_sh_basis_grad.argtypes = [P, P]
@@ -100,8 +111,9 @@ def _grid_args(grid):
     R = _c(grid.reso, np.int32)
     lo = _c(grid.aabb_min, np.float32)
     link = _c(grid.link, np.int32)
-    data = _c(grid.data, np.float32)
-    return (R, lo, float(grid.voxel_size), link, data)
+    deg = int(getattr(grid, "sh_degree", 2))
+    data = _c(grid.data, np.float32).reshape(-1, record_floats(deg))
+    return (R, lo, float(grid.voxel_size), link, data, deg)
 
 
 def _ray_args(rays):
@@ -120,14 +132,14 @@ def set_threads(n: int):
 def render(grid, rays, opts):
     """Forward render: rgb f64[n,3], z-depth f64[n], nsamp i32[n], stats i64[n,3]."""
     lib = _load()
-    R, lo, vs, link, data = _grid_args(grid)
+    R, lo, vs, link, data, deg = _grid_args(grid)
     c2w, intr, off, pix = _ray_args(rays)
     n = rays.n_rays
     rgb = np.zeros((n, 3))
     depth = np.zeros(n)
     nsamp = np.zeros(n, np.int32)
     stats = np.zeros((n, 3), np.int64)
-    lib.orc_render(_p(R), _p(lo), vs, _p(link), _p(data), rays.n_frames, _p(c2w), _p(intr),
+    lib.orc_render(_p(R), _p(lo), vs, _p(link), _p(data), deg, rays.n_frames, _p(c2w), _p(intr),
                    _p(off), _p(pix), n, opts.step_vox, opts.max_samples, opts.t_near,
                    opts.t_stop, opts.color_act, _p(rgb), _p(depth), _p(nsamp), _p(stats))
     return rgb, depth, nsamp, stats
@@ -152,16 +164,17 @@ def loss(rays, rgb, depth, targets, opts):
 
 
 def backward(grid, rays, opts, g_rgb, g_depth, want_grid=True, want_pose=True, flags=None):
-    """Gradients: grid f64[n_alloc,28] (Eq. 6-10) and pose f64[F,6] (Eq. 12-14)."""
+    """Gradients: grid f64[n_alloc, record floats] (Eq. 6-10) and pose
+    f64[F,6] (Eq. 12-14)."""
     lib = _load()
-    R, lo, vs, link, data = _grid_args(grid)
+    R, lo, vs, link, data, deg = _grid_args(grid)
     c2w, intr, off, pix = _ray_args(rays)
     g_rgb = _c(g_rgb, np.float64)
     g_depth = _c(g_depth, np.float64)
-    gd = np.zeros((grid.n_alloc, NREC)) if want_grid else None
+    gd = np.zeros((data.shape[0], record_floats(deg))) if want_grid else None
     gp = np.zeros((rays.n_frames, 6)) if want_pose else None
     fl = opts.flags if flags is None else flags
-    lib.orc_backward(_p(R), _p(lo), vs, _p(link), _p(data), rays.n_frames, _p(c2w), _p(intr),
+    lib.orc_backward(_p(R), _p(lo), vs, _p(link), _p(data), deg, rays.n_frames, _p(c2w), _p(intr),
                      _p(off), _p(pix), rays.n_rays, opts.step_vox, opts.max_samples, opts.t_near,
                      opts.t_stop, opts.color_act, int(fl), _p(g_rgb), _p(g_depth), _p(gd), _p(gp))
     return gd, gp
@@ -180,11 +193,11 @@ def pose_jacobian(grid, rays, opts, flags=None):
     """Per-ray Jacobian f64[n,4,6] of (R, G, B, z-depth) with respect to the
     left se(3) perturbation (rho, phi) of the ray's camera (Eq. 12-14)."""
     lib = _load()
-    R, lo, vs, link, data = _grid_args(grid)
+    R, lo, vs, link, data, deg = _grid_args(grid)
     c2w, intr, off, pix = _ray_args(rays)
     J = np.zeros((rays.n_rays, 4, 6))
     fl = opts.flags if flags is None else flags
-    lib.orc_pose_jacobian(_p(R), _p(lo), vs, _p(link), _p(data), rays.n_frames, _p(c2w), _p(intr),
+    lib.orc_pose_jacobian(_p(R), _p(lo), vs, _p(link), _p(data), deg, rays.n_frames, _p(c2w), _p(intr),
                           _p(off), _p(pix), rays.n_rays, opts.step_vox, opts.max_samples,
                           opts.t_near, opts.t_stop, opts.color_act, int(fl), _p(J))
     return J
@@ -235,11 +248,11 @@ def gn_pose_step(c2w, H, g, damping):
 
 
 def tv(grid, lambda_sigma, lambda_sh, eps, want_grad=True):
-    """Total-variation value and its gradient f64[n_alloc,28]."""
+    """Total-variation value and its gradient f64[n_alloc, record floats]."""
     lib = _load()
-    R, lo, vs, link, data = _grid_args(grid)
-    g = np.zeros((grid.n_alloc, NREC)) if want_grad else None
-    val = lib.orc_tv(_p(R), _p(link), _p(data), float(lambda_sigma), float(lambda_sh),
+    R, lo, vs, link, data, deg = _grid_args(grid)
+    g = np.zeros((data.shape[0], record_floats(deg))) if want_grad else None
+    val = lib.orc_tv(_p(R), _p(link), _p(data), deg, float(lambda_sigma), float(lambda_sh),
                      float(eps), _p(g))
     return float(val), g
 
@@ -247,7 +260,7 @@ def tv(grid, lambda_sigma, lambda_sh, eps, want_grad=True):
 def trace(grid, o, d, opts, cap=4096):
     """Per-sample record of one ray: t, sigma_raw, colour, T_i (n+1), w, (C-hat, D-hat)."""
     lib = _load()
-    R, lo, vs, link, data = _grid_args(grid)
+    R, lo, vs, link, data, deg = _grid_args(grid)
     o = _c(o, np.float64)
     d = _c(d, np.float64)
     t = np.zeros(cap)
@@ -256,7 +269,7 @@ def trace(grid, o, d, opts, cap=4096):
     T = np.zeros(cap + 1)
     w = np.zeros(cap)
     out = np.zeros(4)
-    n = lib.orc_trace(_p(R), _p(lo), vs, _p(link), _p(data), _p(o), _p(d), opts.step_vox,
+    n = lib.orc_trace(_p(R), _p(lo), vs, _p(link), _p(data), deg, _p(o), _p(d), opts.step_vox,
                       opts.max_samples, opts.t_near, opts.t_stop, opts.color_act, cap,
                       _p(t), _p(sr), _p(cs), _p(T), _p(w), _p(out))
     n = min(n, cap)
@@ -265,14 +278,16 @@ def trace(grid, o, d, opts, cap=4096):
 
 
 def interp(grid, q, want_grad=True):
-    """Interpolated 28 values at voxel point q and their Appendix A gradients."""
+    """Interpolated record fields (density, then SH) at voxel point q and
+    their Appendix A gradients; the used fields only (28 at degree 2)."""
     lib = _load()
-    R, lo, vs, link, data = _grid_args(grid)
+    R, lo, vs, link, data, deg = _grid_args(grid)
     q = _c(q, np.float64)
     val = np.zeros(NREC)
-    g = np.zeros((NREC, 3)) if want_grad else None
-    lib.orc_interp(_p(R), _p(lo), vs, _p(link), _p(data), _p(q), _p(val), _p(g))
-    return val, g
+    g = np.zeros((NREC, 3))
+    lib.orc_interp(_p(R), _p(lo), vs, _p(link), _p(data), deg, _p(q), _p(val), _p(g))
+    m = used_fields(deg)
+    return val[:m].copy(), (g[:m].copy() if want_grad else None)
 
 
 def sh_basis(d):
@@ -357,7 +372,7 @@ def rmsprop_grid(data, grad, state, lr_density, lr_sh, alpha, eps):
     state = np.array(state, np.float64)
     g = np.asarray(grad, np.float64)
     touched = np.any(g != 0.0, axis=1)
-    lr = np.full(NREC, float(lr_sh))
+    lr = np.full(g.shape[1], float(lr_sh))
     lr[0] = float(lr_density)
     gt = g[touched]
     v = alpha * state[touched] + (1.0 - alpha) * gt * gt
@@ -412,7 +427,7 @@ def grid_upsample(grid):
     q = np.stack([fx, fy, fz], 1) / 2.0
     c = np.minimum(np.floor(q).astype(np.int64), R - 2)
     f = q - c
-    vals = np.zeros((idx.size, NREC))
+    vals = np.zeros((idx.size, data.shape[1]))
     for b in range(8):
         o = np.array([(b >> 2) & 1, (b >> 1) & 1, b & 1])
         w = np.prod(np.where(o[None, :] == 1, f, 1.0 - f), axis=1)

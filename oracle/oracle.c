@@ -41,18 +41,29 @@
 #endif
 
 #define NREC 28            /* 1 density + 3 channels x 9 SH coefficients (Sec. 5.2) */
-#define NSH 9
+#define NSH 9              /* SH coefficients per channel at degree 2 */
 
 enum { ACT_RELU_SHIFT = 0, ACT_SIGMOID = 1, ACT_IDENTITY = 2 };
 enum { LOSS_L1 = 0, LOSS_L2 = 1 };
 enum { FLAG_POSE_VIEWDIR = 1 };
 
+/*
+ * Record layout.  The paper's records hold nine SH coefficients per channel
+ * (degree 2).  Records of a lower degree d keep the first (d+1)^2 functions
+ * of the same basis (the real SH of degree <= d are a prefix of it):
+ * density, then sh[ch][k] for k < nsh at record[1 + ch*nsh + k], in a record
+ * of `stride` floats (4, 16 or 28; the unused tail of a degree-1 record is
+ * ignored and receives no gradient).
+ */
 typedef struct {
     int32_t R[3];
     double lo[3];
     double vs;
     const int32_t *link;
     const float *data;
+    int nsh;              /* SH coefficients per channel: 1, 4 or 9 */
+    int nrec;             /* used fields: 1 + 3 nsh */
+    int stride;           /* floats per record */
 } ogrid;
 
 typedef struct {
@@ -148,9 +159,10 @@ typedef struct {
     int cell[3];
     double f[3];          /* position inside the cell, [0,1]^3 */
     int64_t idx[8];       /* corner b = 4*i + 2*j + k (x, y, z offsets); -1 empty */
-    double v[8][NREC];    /* corner values, zero for empty links */
+    double v[8][NREC];    /* corner values (first nrec fields), zero for empty links */
     double w[8];          /* trilinear weights */
     int n_alloc_corners;
+    int nrec;             /* fields in use */
 } ocorners;
 
 static void gather_cell(const ogrid *g, const double q[3], ocorners *c)
@@ -163,6 +175,7 @@ static void gather_cell(const ogrid *g, const double q[3], ocorners *c)
         c->f[a] = q[a] - (double)fl;
     }
     c->n_alloc_corners = 0;
+    c->nrec = g->nrec;
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int k = 0; k < 2; ++k) {
@@ -171,8 +184,8 @@ static void gather_cell(const ogrid *g, const double q[3], ocorners *c)
                               + (c->cell[2] + k);
                 int32_t id = g->link[lin];
                 c->idx[b] = id;
-                for (int m = 0; m < NREC; ++m)
-                    c->v[b][m] = id >= 0 ? (double)g->data[(int64_t)id * NREC + m] : 0.0;
+                for (int m = 0; m < g->nrec; ++m)
+                    c->v[b][m] = id >= 0 ? (double)g->data[(int64_t)id * g->stride + m] : 0.0;
                 if (id >= 0) c->n_alloc_corners++;
                 double wx = i ? c->f[0] : 1.0 - c->f[0];
                 double wy = j ? c->f[1] : 1.0 - c->f[1];
@@ -183,7 +196,7 @@ static void gather_cell(const ogrid *g, const double q[3], ocorners *c)
 
 static void interp(const ocorners *c, double out[NREC])
 {
-    for (int m = 0; m < NREC; ++m) {
+    for (int m = 0; m < c->nrec; ++m) {
         double acc = 0.0;
         for (int b = 0; b < 8; ++b) acc += c->w[b] * c->v[b][m];
         out[m] = acc;
@@ -240,7 +253,7 @@ static void build_minv(void)
 static void interp_grad(const ocorners *c, double out[NREC][3])
 {
     const double x = c->f[0], y = c->f[1], z = c->f[2];
-    for (int m = 0; m < NREC; ++m) {
+    for (int m = 0; m < c->nrec; ++m) {
         double a[8];
         for (int r = 0; r < 8; ++r) {
             double acc = 0.0;
@@ -360,7 +373,7 @@ static void march(const ogrid *g, const oopts *op, const double o[3], const doub
         tr->sigma[i] = val[0] > 0.0 ? val[0] : 0.0;
         for (int ch = 0; ch < 3; ++ch) {
             double acc = 0.0;
-            for (int kk = 0; kk < NSH; ++kk) acc += Y[kk] * val[1 + ch * NSH + kk];
+            for (int kk = 0; kk < g->nsh; ++kk) acc += Y[kk] * val[1 + ch * g->nsh + kk];
             tr->s[i][ch] = acc;
             tr->c[i][ch] = act_f(op->act, acc);
         }
@@ -385,14 +398,20 @@ static void march(const ogrid *g, const oopts *op, const double o[3], const doub
 }
 
 static void load_grid(ogrid *g, const int32_t *R, const float *lo, double vs,
-                      const int32_t *link, const float *data)
+                      const int32_t *link, const float *data, int32_t deg)
 {
     for (int a = 0; a < 3; ++a) { g->R[a] = R[a]; g->lo[a] = lo[a]; }
     g->vs = vs;
     g->link = link;
     g->data = data;
+    g->nsh = (deg + 1) * (deg + 1);
+    g->nrec = 1 + 3 * g->nsh;
+    g->stride = deg == 0 ? 4 : deg == 1 ? 16 : NREC;
     if (!g_Minv_ready) build_minv();
 }
+
+/* floats per record of SH degree deg (0, 1 or 2) */
+int orc_record_floats(int32_t deg) { return deg == 0 ? 4 : deg == 1 ? 16 : NREC; }
 
 static int frame_of(const int32_t *off, int32_t F, int64_t r)
 {
@@ -437,10 +456,10 @@ void orc_ray(const double *c2w, const double *intr, int u, int v, double *o, dou
 
 /* Interpolated 28 values and their Eq. 16 gradients at a voxel-unit point. */
 void orc_interp(const int32_t *R, const float *lo, double vs, const int32_t *link,
-                const float *data, const double *q, double *val, double *grad)
+                const float *data, int32_t deg, const double *q, double *val, double *grad)
 {
     ogrid g;
-    load_grid(&g, R, lo, vs, link, data);
+    load_grid(&g, R, lo, vs, link, data, deg);
     ocorners cc;
     gather_cell(&g, q, &cc);
     interp(&cc, val);
@@ -449,13 +468,13 @@ void orc_interp(const int32_t *R, const float *lo, double vs, const int32_t *lin
 
 /* The per-sample record of one ray (for the tests' brute-force sums). */
 int orc_trace(const int32_t *R, const float *lo, double vs, const int32_t *link,
-              const float *data, const double *o, const double *d,
+              const float *data, int32_t deg, const double *o, const double *d,
               double step_vox, int32_t max_samples, double t_near, double t_stop, int32_t act,
               int32_t cap, double *t, double *sigma_raw, double *rgb_s, double *T, double *w,
               double *out_rgb_D)
 {
     ogrid g;
-    load_grid(&g, R, lo, vs, link, data);
+    load_grid(&g, R, lo, vs, link, data, deg);
     oopts op = {step_vox, max_samples, t_near, t_stop, act};
     otrace tr;
     trace_alloc(&tr, 64);
@@ -482,13 +501,13 @@ int orc_trace(const int32_t *R, const float *lo, double vs, const int32_t *link,
  * corners of those, allocated corners of samples with positive raw density.
  */
 void orc_render(const int32_t *R, const float *lo, double vs, const int32_t *link,
-                const float *data, int32_t F, const double *c2w, const double *intr,
+                const float *data, int32_t deg, int32_t F, const double *c2w, const double *intr,
                 const int32_t *off, const int32_t *pix, int64_t n_rays,
                 double step_vox, int32_t max_samples, double t_near, double t_stop, int32_t act,
                 double *rgb, double *depth, int32_t *nsamp, int64_t *stats)
 {
     ogrid g;
-    load_grid(&g, R, lo, vs, link, data);
+    load_grid(&g, R, lo, vs, link, data, deg);
     oopts op = {step_vox, max_samples, t_near, t_stop, act};
 #pragma omp parallel
     {
@@ -593,11 +612,11 @@ static void ray_backward(const ogrid *g, const oopts *op, int32_t flags, const d
             double gval[NREC];
             gval[0] = dL_dsraw;
             for (int ch = 0; ch < 3; ++ch)
-                for (int k = 0; k < NSH; ++k) gval[1 + ch * NSH + k] = dL_ds[ch] * Y[k];
+                for (int k = 0; k < g->nsh; ++k) gval[1 + ch * g->nsh + k] = dL_ds[ch] * Y[k];
             for (int b = 0; b < 8; ++b) {
                 if (cc.idx[b] < 0) continue;
-                double *dst = grad_data + cc.idx[b] * NREC;
-                for (int m = 0; m < NREC; ++m) {
+                double *dst = grad_data + cc.idx[b] * g->stride;
+                for (int m = 0; m < g->nrec; ++m) {
                     double add = cc.w[b] * gval[m];
 #pragma omp atomic
                     dst[m] += add;
@@ -612,7 +631,7 @@ static void ray_backward(const ogrid *g, const oopts *op, int32_t flags, const d
                 double acc = dL_dsraw * G[0][a];
                 for (int ch = 0; ch < 3; ++ch) {
                     double dsa = 0.0;
-                    for (int k = 0; k < NSH; ++k) dsa += Y[k] * G[1 + ch * NSH + k][a];
+                    for (int k = 0; k < g->nsh; ++k) dsa += Y[k] * G[1 + ch * g->nsh + k][a];
                     acc += dL_ds[ch] * dsa;
                 }
                 gp[a] = acc / g->vs;      /* voxel units -> world units */
@@ -625,8 +644,8 @@ static void ray_backward(const ogrid *g, const oopts *op, int32_t flags, const d
                 for (int a = 0; a < 3; ++a) {
                     double acc = 0.0;
                     for (int ch = 0; ch < 3; ++ch)
-                        for (int k = 0; k < NSH; ++k)
-                            acc += dL_ds[ch] * GY[k][a] * val[1 + ch * NSH + k];
+                        for (int k = 0; k < g->nsh; ++k)
+                            acc += dL_ds[ch] * GY[k][a] * val[1 + ch * g->nsh + k];
                     gview[a] += acc;
                 }
             }
@@ -655,14 +674,14 @@ static void ray_backward(const ogrid *g, const oopts *op, int32_t flags, const d
  *     Appendix A spatial gradients, reduced to (rho, phi) per frame.
  */
 void orc_backward(const int32_t *R, const float *lo, double vs, const int32_t *link,
-                  const float *data, int32_t F, const double *c2w, const double *intr,
+                  const float *data, int32_t deg, int32_t F, const double *c2w, const double *intr,
                   const int32_t *off, const int32_t *pix, int64_t n_rays,
                   double step_vox, int32_t max_samples, double t_near, double t_stop, int32_t act,
                   int32_t flags, const double *g_rgb, const double *g_depth,
                   double *grad_data, double *grad_pose)
 {
     ogrid g;
-    load_grid(&g, R, lo, vs, link, data);
+    load_grid(&g, R, lo, vs, link, data, deg);
     oopts op = {step_vox, max_samples, t_near, t_stop, act};
 #pragma omp parallel
     {
@@ -696,13 +715,13 @@ void orc_backward(const int32_t *R, const float *lo, double vs, const int32_t *l
  *   J: [n][4][6], fully written (rows of rays that miss the grid are 0).
  */
 void orc_pose_jacobian(const int32_t *R, const float *lo, double vs, const int32_t *link,
-                       const float *data, int32_t F, const double *c2w, const double *intr,
+                       const float *data, int32_t deg, int32_t F, const double *c2w, const double *intr,
                        const int32_t *off, const int32_t *pix, int64_t n_rays,
                        double step_vox, int32_t max_samples, double t_near, double t_stop,
                        int32_t act, int32_t flags, double *J)
 {
     ogrid g;
-    load_grid(&g, R, lo, vs, link, data);
+    load_grid(&g, R, lo, vs, link, data, deg);
     oopts op = {step_vox, max_samples, t_near, t_stop, act};
 #pragma omp parallel
     {
@@ -733,9 +752,11 @@ void orc_pose_jacobian(const int32_t *R, const float *lo, double vs, const int32
  * and lambda_sh for each of the 27 SH fields.  The gradient is obtained by
  * differentiating each term and adding into the allocated vertices it reads.
  */
-double orc_tv(const int32_t *R, const int32_t *link, const float *data,
+double orc_tv(const int32_t *R, const int32_t *link, const float *data, int32_t deg,
               double lambda_sigma, double lambda_sh, double eps, double *grad)
 {
+    const int nrec = 1 + 3 * (deg + 1) * (deg + 1);
+    const int64_t S = orc_record_floats(deg);
     double total = 0.0;
     const int64_t n = (int64_t)R[0] * R[1] * R[2];
 #pragma omp parallel for reduction(+ : total) schedule(static)
@@ -749,33 +770,33 @@ double orc_tv(const int32_t *R, const int32_t *link, const float *data,
         int32_t nx = link[lin + (int64_t)R[1] * R[2]];
         int32_t ny = link[lin + R[2]];
         int32_t nz = link[lin + 1];
-        for (int m = 0; m < NREC; ++m) {
+        for (int m = 0; m < nrec; ++m) {
             double lam = m == 0 ? lambda_sigma : lambda_sh;
-            double v0 = data[(int64_t)id * NREC + m];
-            double vx = nx >= 0 ? data[(int64_t)nx * NREC + m] : 0.0;
-            double vy = ny >= 0 ? data[(int64_t)ny * NREC + m] : 0.0;
-            double vz = nz >= 0 ? data[(int64_t)nz * NREC + m] : 0.0;
+            double v0 = data[(int64_t)id * S + m];
+            double vx = nx >= 0 ? data[(int64_t)nx * S + m] : 0.0;
+            double vy = ny >= 0 ? data[(int64_t)ny * S + m] : 0.0;
+            double vz = nz >= 0 ? data[(int64_t)nz * S + m] : 0.0;
             double dx = vx - v0, dy = vy - v0, dz = vz - v0;
             double root = sqrt(dx * dx + dy * dy + dz * dz + eps);
             total += lam * root;
             if (grad) {
                 double g0 = -lam * (dx + dy + dz) / root;
 #pragma omp atomic
-                grad[(int64_t)id * NREC + m] += g0;
+                grad[(int64_t)id * S + m] += g0;
                 if (nx >= 0) {
                     double gx = lam * dx / root;
 #pragma omp atomic
-                    grad[(int64_t)nx * NREC + m] += gx;
+                    grad[(int64_t)nx * S + m] += gx;
                 }
                 if (ny >= 0) {
                     double gy = lam * dy / root;
 #pragma omp atomic
-                    grad[(int64_t)ny * NREC + m] += gy;
+                    grad[(int64_t)ny * S + m] += gy;
                 }
                 if (nz >= 0) {
                     double gz = lam * dz / root;
 #pragma omp atomic
-                    grad[(int64_t)nz * NREC + m] += gz;
+                    grad[(int64_t)nz * S + m] += gz;
                 }
             }
         }

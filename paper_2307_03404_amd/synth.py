@@ -46,11 +46,34 @@ class Grid:
     aabb_min: np.ndarray   # f32[3], world position of vertex (0,0,0)
     voxel_size: float      # world length of one voxel edge
     link: np.ndarray       # i32[Rx*Ry*Rz], index (x*Ry+y)*Rz+z, -1 = empty
-    data: np.ndarray       # f32[n_alloc][28]: density, then sh[ch][k]
+    data: np.ndarray       # f32[n_alloc][record_floats(sh_degree)]: density, then sh[ch][k]
+    sh_degree: int = 2     # 2: the paper's nine coefficients per channel; 0 or 1: the first 1 or 4
 
     @property
     def n_alloc(self) -> int:
         return int(self.data.shape[0])
+
+
+def record_floats(sh_degree: int) -> int:
+    """Floats per vertex record: density + 3 (d+1)^2 SH coefficients, padded
+    to a multiple of four (16-byte records): 4, 16 (13 used) or 28."""
+    return {0: 4, 1: 16, 2: 28}[int(sh_degree)]
+
+
+def with_sh_degree(grid: Grid, sh_degree: int) -> Grid:
+    """The same map with records of a lower SH degree: the density and the
+    first (d+1)^2 coefficients of each channel, the padding zeroed."""
+    d = int(sh_degree)
+    if d == grid.sh_degree:
+        return grid
+    assert d < grid.sh_degree, "only lowers the degree"
+    k_old, k_new = (grid.sh_degree + 1) ** 2, (d + 1) ** 2
+    src = np.asarray(grid.data, np.float32)
+    out = np.zeros((src.shape[0], record_floats(d)), np.float32)
+    out[:, 0] = src[:, 0]
+    for c in range(3):
+        out[:, 1 + c * k_new:1 + (c + 1) * k_new] = src[:, 1 + c * k_old:1 + c * k_old + k_new]
+    return dataclasses.replace(grid, data=out, sh_degree=d)
 
 
 @dataclass

@@ -11,7 +11,10 @@ the shifted-ReLU derivative tested at s > 0 instead of s + 1/2 > 0, a
 backward that ignores early termination or the sample cap its forward
 applied, an exclusive instead of inclusive prefix in Eq. 9/10, T_i instead
 of T_{i+1}, the position chain of Eq. 14 without the t_i factor, and the
-sign of the L1 depth derivative.
+sign of the L1 depth derivative; and, for records of SH degree 0 and 1, a
+channel offset that keeps the degree-2 stride of nine, a record stride that
+ignores the padding of degree-1 records, and a gradient scattered with the
+degree-2 record stride.
 """
 import os
 import subprocess
@@ -23,7 +26,8 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
-PINS = ["tests/test_oracle_pins_workload_settings.py", "tests/test_oracle_pins.py"]
+PINS = ["tests/test_oracle_pins_workload_settings.py", "tests/test_oracle_pins.py",
+        "tests/test_oracle_pins_sh_degree.py"]
 
 MUTATIONS = {
     "relu_shift_derivative_at_s_gt_0": (
@@ -54,6 +58,18 @@ MUTATIONS = {
         "drho = e > 0.0 ? 1.0 : (e < 0.0 ? -1.0 : 0.0);",
         "drho = e > 0.0 ? -1.0 : (e < 0.0 ? 1.0 : 0.0);",
         "loss_gradient_fd"),
+    "reduced_degree_channel_offset_of_nine": (
+        "for (int kk = 0; kk < g->nsh; ++kk) acc += Y[kk] * val[1 + ch * g->nsh + kk];",
+        "for (int kk = 0; kk < g->nsh; ++kk) acc += Y[kk] * val[1 + ch * NSH + kk];",
+        "degree0 or degree1 or reduced_degree"),
+    "degree1_record_without_padding": (
+        "g->stride = deg == 0 ? 4 : deg == 1 ? 16 : NREC;",
+        "g->stride = deg == 0 ? 4 : deg == 1 ? 13 : NREC;",
+        "degree1 or reduced_degree"),
+    "reduced_degree_gradient_with_degree2_stride": (
+        "double *dst = grad_data + cc.idx[b] * g->stride;",
+        "double *dst = grad_data + cc.idx[b] * (g->stride < NREC ? g->nrec : g->stride);",
+        "degree1_grid_backward or reduced_degree"),
 }
 
 
