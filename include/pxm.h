@@ -28,10 +28,14 @@
  *
  * Grid (Sec. 5.2, model representation).  A lattice of Rx x Ry x Rz
  * vertices; vertex (i,j,k) sits at aabb_min + voxel_size * (i,j,k).  Each
- * allocated vertex holds 28 floats: the density followed by nine degree-2
- * spherical-harmonic coefficients for each colour channel (record[1+9c+k]).
- * Samples are trilinearly interpolated from the 8 closest vertices (Fig. 4,
- * Appendix A); an empty vertex (link -1) reads as zero.
+ * allocated vertex holds the density followed by the spherical-harmonic
+ * coefficients of each colour channel: at the paper's degree 2, nine per
+ * channel in a record of 28 floats (record[1+9c+k]).  Lower degrees d = 0, 1
+ * keep the first (d+1)^2 functions of the same basis per channel
+ * (record[1+(d+1)^2 c+k]) in records of PXM_RECORD_FLOATS(d) = 4 or 16 floats
+ * (at d = 1 the last three floats are padding: never read as SH, never given
+ * a gradient).  Samples are trilinearly interpolated from the 8 closest
+ * vertices (Fig. 4, Appendix A); an empty vertex (link -1) reads as zero.
  *
  * Ray model (Sec. 4).  Pixel (u,v) of frame f defines
  *   d_cam = ((u + 0.5 - cx) / fx, (v + 0.5 - cy) / fy, 1)  (OpenCV axes),
@@ -52,8 +56,9 @@
 extern "C" {
 #endif
 
-#define PXM_ABI_VERSION 5   /* 5: two-launch fused variant; per-ray workspace */
-#define PXM_RECORD 28          /* floats per vertex: density + 3 x 9 SH */
+#define PXM_ABI_VERSION 6   /* 6: SH degree 0/1 records (pxm_grid.sh_degree) */
+#define PXM_RECORD 28          /* floats per vertex at SH degree 2: density + 3 x 9 SH */
+#define PXM_RECORD_FLOATS(d) ((d) == 0 ? 4 : (d) == 1 ? 16 : 28)   /* per SH degree */
 
 typedef enum {
     PXM_OK = 0,
@@ -86,11 +91,13 @@ typedef struct {
     float voxel_size;       /* world edge length of one voxel, > 0 */
     const int32_t *link;    /* [Rx*Ry*Rz], index (x*Ry + y)*Rz + z -> record id or -1 */
     int64_t n_alloc;        /* number of records (0: an empty map, every link -1) */
-    const float *data;      /* [n_alloc][28], 16-byte aligned; may be NULL when n_alloc == 0,
-                               as may every grad_data argument */
+    const float *data;      /* [n_alloc][PXM_RECORD_FLOATS(sh_degree)], 16-byte aligned; may be
+                               NULL when n_alloc == 0, as may every grad_data argument (grad_data
+                               arrays have the same layout as data) */
     const uint32_t *occ;    /* optional occupancy bitfield from pxm_build_occupancy for THIS
                                link table, or NULL.  Lets the march step over empty cells and
                                8^3-cell bricks; results are identical with or without it. */
+    int32_t sh_degree;      /* SH degree of the records: 2 (the paper's), 1 or 0 */
 } pxm_grid;
 
 typedef struct {
@@ -133,7 +140,7 @@ int pxm_render_forward(const pxm_grid *grid, const pxm_rays *rays, const pxm_opt
  *   dL/d sigma_raw,i = 1[sigma_raw,i > 0] delta [g_C.(c_i T_{i+1} - C-hat + sum_{j<=i} c_j w_j)
  *                                                + g_D (t_i T_{i+1} - D-hat + sum_{j<=i} t_j w_j)]
  *   dL/d SH_k,c,i    = act'(s_c,i) w_i g_C,c Y_k(d)
- * through the trilinear weights into grad_data [n_alloc][28] (accumulated;
+ * through the trilinear weights into grad_data [n_alloc][S] (accumulated;
  * empty vertices receive nothing).  Rays with all-zero upstream gradients are skipped.
  */
 int pxm_render_backward_grid(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
@@ -163,8 +170,8 @@ int pxm_render_backward_pose(const pxm_grid *grid, const pxm_rays *rays, const p
  *   TV = sum_m lambda_m sum_v sqrt(dx_m(v)^2 + dy_m(v)^2 + dz_m(v)^2 + eps),
  * forward differences to the +x/+y/+z neighbours (empty reads as 0), v
  * allocated and not on an upper face, lambda_0 = lambda_density for the
- * density field and lambda_sh for each of the 27 SH fields.  dTV/d record is
- * added into grad_data [n_alloc][28] (accumulated, gather form: one writer
+ * density field and lambda_sh for each SH field (27 at degree 2).  dTV/d
+ * record is added into grad_data [n_alloc][S] (accumulated, gather form: one writer
  * per vertex, no atomics).  With grid->occ set, 8^3 bricks whose cells have
  * no allocated corner are skipped.
  */
@@ -180,7 +187,7 @@ int pxm_tv_grad(const pxm_grid *grid, float lambda_density, float lambda_sh, flo
  *   tgt_rgb [n_rays][3], tgt_depth [n_rays], frame_weight [F]      (in)
  *   rgb, depth   [n_rays][3], [n_rays]       (out, may be NULL)
  *   loss         [F] float64                 (accumulated, may be NULL)
- *   grad_data    [n_alloc][28]               (accumulated; required with PXM_WANT_GRID)
+ *   grad_data    [n_alloc][S]                (accumulated; required with PXM_WANT_GRID)
  *   grad_pose    [F][6] float64              (accumulated; required with PXM_WANT_POSE)
  *   stats        [4] int64                   (accumulated with PXM_WANT_STATS:
  *                 occupied samples, allocated corners of those, allocated
@@ -241,19 +248,22 @@ int pxm_pose_gn(int32_t n_frames, float *c2w, double *gn, float damping, void *s
 
 /*
  * Mapping update (Sec. 5.4: RMSProp for mapping): one sparse RMSProp step
- * over the vertex records.  A record is touched when any of its 28 entries
- * of grad_data is non-zero; for touched records, entry by entry,
+ * over the vertex records of SH degree sh_degree (S = PXM_RECORD_FLOATS(
+ * sh_degree) floats each).  A record is touched when any of its S entries of
+ * grad_data is non-zero; for touched records, entry by entry,
  *   state <- alpha state + (1 - alpha) g^2,
  *   data  <- data - lr g / (sqrt(state) + eps),
- * with lr = lr_density for entry 0 and lr_sh for the 27 SH entries.
+ * with lr = lr_density for entry 0 and lr_sh for the SH entries (padding
+ * entries have a zero gradient and do not move).
  * Untouched records keep their values and running averages (the rule of the
  * Plenoxel optimiser the method builds on; the paper states none).
  * grad_data is read and then zeroed, so one call ends a mapping iteration.
- *   data, grad_data, state [n_alloc][28] f32, 16-byte aligned (in/out;
+ *   data, grad_data, state [n_alloc][S] f32, 16-byte aligned (in/out;
  *   state starts zeroed).  n_alloc == 0 is a no-op.
  */
-int pxm_grid_rmsprop(int64_t n_alloc, float *data, float *grad_data, float *state,
-                     float lr_density, float lr_sh, float alpha, float eps, void *stream);
+int pxm_grid_rmsprop(int64_t n_alloc, int32_t sh_degree, float *data, float *grad_data,
+                     float *state, float lr_density, float lr_sh, float alpha, float eps,
+                     void *stream);
 
 /*
  * Occupancy bitfield for empty-space skipping (an exact acceleration: a cell
@@ -305,7 +315,7 @@ int pxm_grid_upsample_link(const pxm_grid *grid, int32_t *link_fine, int64_t *n_
  * rendering the fine grid at twice the step_vox reproduces the coarse render.
  *   link_fine  the table step 1 wrote for this grid
  *   n_fine     its count (host value, read back by the caller)
- *   data_fine  [n_fine][28] f32, 16-byte aligned, written
+ *   data_fine  [n_fine][S] f32 (the grid's record layout), 16-byte aligned, written
  */
 int pxm_grid_upsample_data(const pxm_grid *grid, const int32_t *link_fine, int64_t n_fine,
                            float *data_fine, void *stream);
@@ -315,7 +325,7 @@ int pxm_grid_upsample_data(const pxm_grid *grid, const int32_t *link_fine, int64
  * order and are renumbered 0 .. n_out-1, and the link table is rewritten
  * (dropped or invalid links -> -1).
  *   link_out  [Rx*Ry*Rz] int32, written; may be grid->link itself (in place)
- *   data_out  [n_alloc][28] f32 capacity, 16-byte aligned, must not overlap
+ *   data_out  [n_alloc][S] f32 capacity, 16-byte aligned, must not overlap
  *             grid->data; rows [0, n_out) are written
  *   n_out     device int64, written
  * tau = -inf keeps every record.  NaN tau is PXM_INVALID_ARGUMENT.

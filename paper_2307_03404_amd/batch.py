@@ -317,7 +317,7 @@ class MappingLoop:
         if self.tv[0] or self.tv[1]:
             pxm.tv_grad(self.grid, self.tv[0], self.tv[1], self.tv[2], self.grad)
         pxm.grid_rmsprop(self.grid.data, self.grad, self.state, self.lr[0], self.lr[1],
-                         self.alpha, self.eps)
+                         self.alpha, self.eps, sh_degree=self.grid.sh_degree)
         return self.loss.sum()
 
 

@@ -41,6 +41,8 @@ int check_grid(const pxm_grid* g, bool need_payload = true) {
     if (!(g->voxel_size > 0.f) || !finite(g->voxel_size))
         return fail(PXM_INVALID_ARGUMENT, "voxel_size must be finite and > 0");
     if (!g->link) return fail(PXM_INVALID_ARGUMENT, "grid.link is NULL");
+    if (g->sh_degree < 0 || g->sh_degree > 2)
+        return fail(PXM_INVALID_ARGUMENT, "sh_degree = %d not in {0, 1, 2}", g->sh_degree);
     if (g->n_alloc < 0 || g->n_alloc > 2147483647LL)
         return fail(PXM_INVALID_ARGUMENT, "n_alloc = %lld outside [0, 2^31)", (long long)g->n_alloc);
     if (need_payload && g->n_alloc > 0 && !g->data)
@@ -77,6 +79,7 @@ int check_opts(const pxm_opts* o) {
 
 pxm::KGrid kgrid(const pxm_grid* g) {
     pxm::KGrid k;
+    k.deg = g->sh_degree;
     for (int a = 0; a < 3; ++a) {
         k.R[a] = g->reso[a];
         k.lo[a] = (double)g->aabb_min[a];
@@ -308,9 +311,11 @@ int pxm_pose_gn(int32_t n_frames, float* c2w, double* gn, float damping, void* s
     return launched(pxm::launch_pose_gn(n_frames, c2w, gn, damping, (hipStream_t)stream), "pose_gn");
 }
 
-int pxm_grid_rmsprop(int64_t n_alloc, float* data, float* grad_data, float* state, float lr_density,
-                     float lr_sh, float alpha, float eps, void* stream) {
+int pxm_grid_rmsprop(int64_t n_alloc, int32_t sh_degree, float* data, float* grad_data, float* state,
+                     float lr_density, float lr_sh, float alpha, float eps, void* stream) {
     if (n_alloc < 0 || n_alloc > INT32_MAX) return fail(PXM_INVALID_ARGUMENT, "n_alloc outside [0, 2^31)");
+    if (sh_degree < 0 || sh_degree > 2)
+        return fail(PXM_INVALID_ARGUMENT, "sh_degree = %d not in {0, 1, 2}", sh_degree);
     if (!finite(lr_density) || !finite(lr_sh) || !(lr_density >= 0.f) || !(lr_sh >= 0.f))
         return fail(PXM_INVALID_ARGUMENT, "learning rates must be finite and >= 0");
     if (!(alpha >= 0.f && alpha < 1.f)) return fail(PXM_INVALID_ARGUMENT, "alpha outside [0, 1)");
@@ -319,8 +324,8 @@ int pxm_grid_rmsprop(int64_t n_alloc, float* data, float* grad_data, float* stat
     if (!data || !grad_data || !state) return fail(PXM_INVALID_ARGUMENT, "a required array is NULL");
     if (((uintptr_t)data | (uintptr_t)grad_data | (uintptr_t)state) & 15u)
         return fail(PXM_INVALID_ARGUMENT, "data, grad_data and state must be 16-byte aligned");
-    return launched(pxm::launch_rmsprop(n_alloc, data, grad_data, state, lr_density, lr_sh, alpha,
-                                        eps, (hipStream_t)stream), "grid_rmsprop");
+    return launched(pxm::launch_rmsprop(n_alloc, sh_degree, data, grad_data, state, lr_density, lr_sh,
+                                        alpha, eps, (hipStream_t)stream), "grid_rmsprop");
 }
 
 size_t pxm_grid_edit_workspace_bytes(const pxm_grid* grid) {
@@ -392,7 +397,7 @@ int pxm_grid_prune(const pxm_grid* grid, float tau, int32_t* link_out, float* da
         if (!data_out) return fail(PXM_INVALID_ARGUMENT, "data_out is NULL");
         if (reinterpret_cast<uintptr_t>(data_out) & 15)
             return fail(PXM_INVALID_ARGUMENT, "data_out must be 16-byte aligned");
-        const uintptr_t bytes = (uintptr_t)grid->n_alloc * PXM_RECORD * 4;
+        const uintptr_t bytes = (uintptr_t)grid->n_alloc * PXM_RECORD_FLOATS(grid->sh_degree) * 4;
         const uintptr_t a0 = reinterpret_cast<uintptr_t>(data_out), b0 = reinterpret_cast<uintptr_t>(grid->data);
         if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(PXM_INVALID_ARGUMENT, "data_out overlaps grid.data");
     }

@@ -83,7 +83,7 @@ __device__ __forceinline__ void finish_chunk(uint32_t bits, int64_t gw, int64_t 
 
 // Record r survives iff its density exceeds tau.  Pass `it` of wave w covers
 // 64 consecutive records, i.e. words 8 it + 2w and 8 it + 2w + 1 of the chunk.
-__global__ __launch_bounds__(EDIT_THREADS) void k_keep_flags(const float* __restrict__ data, float tau, int64_t n,
+__global__ __launch_bounds__(EDIT_THREADS) void k_keep_flags(const float* __restrict__ data, int S, float tau, int64_t n,
                                                              uint32_t* __restrict__ words, int32_t* __restrict__ wpre,
                                                              int32_t* __restrict__ chunk_total) {
     __shared__ uint32_t s_words[EDIT_WORDS];
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(EDIT_THREADS) void k_keep_flags(const float* __rest
     const int lane = lane_id(), w = threadIdx.x / WAVE;
     for (int it = 0; it < KEEP_ITERS; ++it) {
         const int64_t r = base + it * EDIT_THREADS + threadIdx.x;
-        const bool f = r < n && data[r * REC] > tau;
+        const bool f = r < n && data[r * S] > tau;
         const unsigned long long m = __ballot(f);
         if (lane == 0) s_words[it * 8 + 2 * w] = (uint32_t)m;
         if (lane == 32) s_words[it * 8 + 2 * w + 1] = (uint32_t)(m >> 32);
@@ -139,8 +139,9 @@ __device__ __forceinline__ int32_t compact_id(const uint32_t* words, const int32
     return chunk_off[w / EDIT_WORDS] + wpre[w] + __popc(bits & ((1u << b) - 1u));
 }
 
-// 8 lanes per record (7 carry a float4): new id, remap entry, copy.
-__global__ __launch_bounds__(EDIT_THREADS) void k_prune_copy(const float* __restrict__ data, int64_t n,
+// 8 lanes per record: lanes p < S/4 copy float4 p of it (at most 7), lane 7
+// writes its remap entry.
+__global__ __launch_bounds__(EDIT_THREADS) void k_prune_copy(const float* __restrict__ data, int S, int64_t n,
                                                              const uint32_t* __restrict__ words,
                                                              const int32_t* __restrict__ wpre,
                                                              const int32_t* __restrict__ chunk_off,
@@ -152,9 +153,9 @@ __global__ __launch_bounds__(EDIT_THREADS) void k_prune_copy(const float* __rest
         const int32_t id = compact_id(words, wpre, chunk_off, r);
         if (part == 7) {
             remap[r] = id;
-        } else if (id >= 0) {
-            reinterpret_cast<float4*>(out + (int64_t)id * REC)[part] =
-                reinterpret_cast<const float4*>(data + r * REC)[part];
+        } else if (id >= 0 && part < S / 4) {
+            reinterpret_cast<float4*>(out + (int64_t)id * S)[part] =
+                reinterpret_cast<const float4*>(data + r * S)[part];
         }
     }
 }
@@ -295,8 +296,9 @@ __global__ __launch_bounds__(EDIT_THREADS) void k_fine_link(Lattice L, int64_t n
 // coarse cell v (o' a subset of o's bits; weight 1/2 per odd axis).  A group
 // of 8 lanes takes one v: lane k first fetches corner link v + o_k and the id
 // of fine vertex 2v + o_k, for UNIT_BATCHES batches of 8 vertices at once;
-// then, per batch with an allocated fine vertex, lane p < 7 fetches float4 p
-// of the 8 corner records and writes float4 p of each allocated fine record.
+// then, per batch with an allocated fine vertex, lane p < S/4 (7 at SH degree
+// 2) fetches float4 p of the 8 corner records and writes float4 p of each
+// allocated fine record.
 // Sums run over corners in (x, y, z) bit order in FP64.
 __global__ __launch_bounds__(EDIT_THREADS) void k_fine_data(KGrid g, Lattice L, const int32_t* __restrict__ link_fine,
                                                             int64_t n_fine, float* __restrict__ out) {
@@ -304,6 +306,7 @@ __global__ __launch_bounds__(EDIT_THREADS) void k_fine_data(KGrid g, Lattice L, 
     const int64_t nc = (int64_t)L.R[0] * L.R[1] * L.R[2];
     const int64_t waves = (int64_t)gridDim.x * (EDIT_THREADS / WAVE);
     const float4* data4 = reinterpret_cast<const float4*>(g.data);
+    const int S = record_floats(g.deg), Q = S / 4;   // float4 parts per record (at most 7)
     // neighbouring units write records that share cache lines: keep them on one XCD
     const int64_t first = xcd_tile(blockIdx.x, gridDim.x) * (EDIT_THREADS / WAVE) + threadIdx.x / WAVE;
     for (int64_t s = first; s * 8 * UNIT_BATCHES < nc; s += waves) {
@@ -327,19 +330,19 @@ __global__ __launch_bounds__(EDIT_THREADS) void k_fine_data(KGrid g, Lattice L, 
         for (int j = 0; j < UNIT_BATCHES; ++j) {
             const int32_t lid = lids[j], fid = fids[j];
             if (__ballot(link_ok(fid, n_fine)) == 0ull) continue;
-            const int p = k;   // float4 part handled by this lane (7 = none)
+            const int p = k;   // float4 part handled by this lane (none when p >= Q)
             float4 v[8];
             bool ok[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int32_t lb = __shfl(lid, gbase + b, WAVE);
                 ok[b] = link_ok(lb, g.n_alloc);
-                v[b] = (ok[b] && p < 7) ? data4[(int64_t)lb * (REC / 4) + p] : make_float4(0.f, 0.f, 0.f, 0.f);
+                v[b] = (ok[b] && p < Q) ? data4[(int64_t)lb * Q + p] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 const int32_t fo = __shfl(fid, gbase + o, WAVE);
-                if (!link_ok(fo, n_fine) || p == 7) continue;
+                if (!link_ok(fo, n_fine) || p >= Q) continue;
                 const double wt = 1.0 / (double)(1 << __popc(o));
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(EDIT_THREADS) void k_fine_data(KGrid g, Lattice L, 
                     a3 += wt * (double)v[b].w;
                 }
                 if (p == 0) a0 *= 0.5;
-                reinterpret_cast<float4*>(out + (int64_t)fo * REC)[p] =
+                reinterpret_cast<float4*>(out + (int64_t)fo * S)[p] =
                     make_float4((float)a0, (float)a1, (float)a2, (float)a3);
             }
         }
@@ -449,13 +452,15 @@ hipError_t launch_prune(const KGrid& g, float tau, int32_t* link_out, float* dat
     int32_t* remap = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + compaction_words_bytes(nw));
     hipError_t e;
     if (c.n_chunks > 0) {
-        hipLaunchKernelGGL(k_keep_flags, dim3((unsigned)c.n_chunks), dim3(EDIT_THREADS), 0, st, g.data, tau, n, c.words,
+        hipLaunchKernelGGL(k_keep_flags, dim3((unsigned)c.n_chunks), dim3(EDIT_THREADS), 0, st, g.data,
+                           record_floats(g.deg), tau, n, c.words,
                            c.wpre, c.chunk);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = scan(c, n_out, st)) != hipSuccess) return e;
     if (n > 0) {
-        hipLaunchKernelGGL(k_prune_copy, dim3(stride_blocks(n * 8)), dim3(EDIT_THREADS), 0, st, g.data, n, c.words,
+        hipLaunchKernelGGL(k_prune_copy, dim3(stride_blocks(n * 8)), dim3(EDIT_THREADS), 0, st, g.data,
+                           record_floats(g.deg), n, c.words,
                            c.wpre, c.chunk, remap, data_out);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

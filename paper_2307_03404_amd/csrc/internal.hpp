@@ -78,8 +78,8 @@ hipError_t launch_gn(const KGrid& g, const KRays& rs, const KOpts& op, const flo
                      const float* tgt_depth, const float* frame_weight, double* gn, hipStream_t st);
 hipError_t launch_pose_gn(int F, float* c2w, double* gn, float mu, hipStream_t st);
 
-hipError_t launch_rmsprop(int64_t n, float* data, float* grad, float* avg, float lr_d, float lr_sh,
-                          float alpha, float eps, hipStream_t st);
+hipError_t launch_rmsprop(int64_t n, int deg, float* data, float* grad, float* avg, float lr_d,
+                          float lr_sh, float alpha, float eps, hipStream_t st);
 
 // Dynamic-grid edits: flags are compacted in chunks of EDIT_CHUNK items
 // (one workgroup).  Workspace bytes of a prune of n_alloc records and of the

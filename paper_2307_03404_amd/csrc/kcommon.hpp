@@ -2,9 +2,11 @@
 //
 // Layout in HBM
 //   link  int32 [Rx*Ry*Rz]    vertex (x,y,z) -> record id, -1 = empty
-//   data  f32   [n][28]       density, then SH[c][k] for c = 0..2, k = 0..8
-//   grad  f32   [n][28]       same layout as data
-// Records are 112 bytes and 16-byte aligned, so a corner is 7 float4 loads.
+//   data  f32   [n][S]        density, then SH[c][k] for c = 0..2, k < (d+1)^2
+//   grad  f32   [n][S]        same layout as data
+// At the paper's SH degree d = 2 a record is 28 floats (112 bytes, 7 float4
+// loads); degree 1 keeps 13 of a 16-float record, degree 0 is 4 floats.
+// Records are 16-byte aligned.
 //
 // Precision plan
 //   * ray direction and sample positions in FP64: a voxel coordinate near 512
@@ -22,14 +24,31 @@
 
 namespace pxm {
 
-constexpr int REC = 28;
+constexpr int REC = 28;          // floats per record at SH degree 2 (the largest)
 constexpr int WAVE = 64;
+
+// Record layout of SH degree DEG: the first (DEG+1)^2 functions of the
+// degree-2 basis per channel (the real SH of degree <= DEG are a prefix of
+// it), padded to whole float4s.
+template <int DEG>
+struct RecL {
+    static constexpr int NSH = (DEG + 1) * (DEG + 1);   // coefficients per channel
+    static constexpr int USED = 1 + 3 * NSH;            // density + SH fields
+    static constexpr int S = DEG == 0 ? 4 : DEG == 1 ? 16 : 28;   // floats per record
+    static constexpr int Q = S / 4;                     // float4 per record
+};
 
 enum { ACT_RELU_SHIFT = 0, ACT_SIGMOID = 1, ACT_IDENTITY = 2 };
 enum { LOSS_L1 = 0, LOSS_L2 = 1 };
 
+// Floats per record of SH degree deg (RecL<deg>::S at run time).
+__host__ __device__ __forceinline__ int record_floats(int deg) {
+    return deg == 0 ? 4 : deg == 1 ? 16 : 28;
+}
+
 struct KGrid {
     int R[3];
+    int deg;                    // SH degree of the records (0, 1 or 2)
     int64_t sx, sy;             // link strides of +x and +y (the +z stride is 1)
     double lo[3];               // aabb_min
     double inv_vs;              // 1 / voxel_size
@@ -372,10 +391,11 @@ __device__ __forceinline__ int load_links(const KGrid& g, int64_t base, int idx[
     return n;
 }
 
+template <int DEG>
 __device__ __forceinline__ void load_record(const float* __restrict__ data, int id, float rec[REC]) {
-    const float4* p = reinterpret_cast<const float4*>(data + (int64_t)id * REC);
+    const float4* p = reinterpret_cast<const float4*>(data + (int64_t)id * RecL<DEG>::S);
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
+    for (int q = 0; q < RecL<DEG>::Q; ++q) {
         float4 v = p[q];
         rec[4 * q] = v.x; rec[4 * q + 1] = v.y; rec[4 * q + 2] = v.z; rec[4 * q + 3] = v.w;
     }
@@ -393,9 +413,10 @@ struct Interp {
     float ev[3][3];     // sum_b w_b sum_k dY_k/dd_a SH_{b,c,k}  VIEW only
 };
 
-template <bool GRAD, bool VIEW>
+template <bool GRAD, bool VIEW, int DEG>
 __device__ __forceinline__ void gather_interp(const KGrid& g, const int idx[8], const float Y[9],
                                               const float GY[9][3], const float f[3], Interp& v) {
+    constexpr int NSH = RecL<DEG>::NSH;
     v.sig = 0.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -414,13 +435,13 @@ __device__ __forceinline__ void gather_interp(const KGrid& g, const int idx[8], 
         const float wx = bx ? x1 : x0, wy = by ? y1 : y0, wz = bz ? z1 : z0;
         const float w = (wx * wy) * wz;
         float rec[REC];
-        load_record(g.data, idx[b], rec);
+        load_record<DEG>(g.data, idx[b], rec);
         float e[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             float acc = 0.0f;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) acc = fmaf(Y[k], rec[1 + 9 * c + k], acc);
+            for (int k = 0; k < NSH; ++k) acc = fmaf(Y[k], rec[1 + NSH * c + k], acc);
             e[c] = acc;
         }
         v.sig = fmaf(w, rec[0], v.sig);
@@ -444,7 +465,7 @@ __device__ __forceinline__ void gather_interp(const KGrid& g, const int idx[8], 
                 for (int a = 0; a < 3; ++a) {
                     float acc = 0.f;
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) acc = fmaf(GY[k][a], rec[1 + 9 * c + k], acc);
+                    for (int k = 0; k < NSH; ++k) acc = fmaf(GY[k][a], rec[1 + NSH * c + k], acc);
                     v.ev[c][a] = fmaf(w, acc, v.ev[c][a]);
                 }
         }

@@ -13,6 +13,7 @@
 // (Sec. 5.3): per-ray pose Jacobians of the four outputs from the same march,
 // reduced to per-frame normal equations.
 #include <atomic>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "scatter.hpp"
@@ -43,6 +44,7 @@ struct FwdResult {
 // position k_first + o, in words marks[w * WAVE] (w < MARK_WORDS) written
 // in order from a register; out.mark_last is the last word written and
 // out.mark_overflow is set if a marked position lay beyond the mask.
+template <int DEG>
 __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, const Ray& ray,
                                             const float Y[9], FwdResult& out,
                                             uint32_t* marks = nullptr, int64_t mstride = WAVE) {
@@ -100,7 +102,7 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
             const int na = load_links(g, s.base, idx);
             if (na == 0) continue;
             Interp v;
-            gather_interp<false, false>(g, idx, Y, nullptr, s.f, v);
+            gather_interp<false, false, DEG>(g, idx, Y, nullptr, s.f, v);
             const float sr = v.sig, s0 = v.s[0], s1 = v.s[1], s2 = v.s[2];
             ++occ;
             occc += na;
@@ -147,7 +149,7 @@ struct BwdState {
 // Backward work of one occupied sample (Eq. 6-14): updates the running state
 // and the pose accumulators; returns true with the sample's grid-gradient
 // factors (gsig = dL/d sigma_raw, gs = dL/ds_c) when it carries light.
-template <bool POSE, bool VIEW>
+template <bool POSE, bool VIEW, int DEG>
 __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op, const Ray& ray,
                                                 const float Y[9], const float GY[9][3],
                                                 const Sample& s, const double Chat[3], double Dhat,
@@ -156,7 +158,7 @@ __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op,
                                                 float gs[3]) {
     if (load_links(g, s.base, idx) == 0) return false;
     Interp v;
-    gather_interp<POSE, POSE && VIEW>(g, idx, Y, GY, s.f, v);
+    gather_interp<POSE, POSE && VIEW, DEG>(g, idx, Y, GY, s.f, v);
     trilinear_weights(s.f, w);
     const float sr = v.sig;
     if (!(sr > 0.f)) return false;      // sigma = 0: no light, zero gradient (ReLU)
@@ -226,7 +228,7 @@ __device__ __forceinline__ int next_mark(const uint32_t* marks, int last, int o)
 // every lane must call this (lanes without a ray pass n = 0); steps where no
 // lane has an occupied cell are jumped over together.  Without GRID every
 // lane marches on its own.
-template <bool GRID, bool POSE, bool VIEW>
+template <bool GRID, bool POSE, bool VIEW, int DEG>
 __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, const Ray& ray,
                                              const float Y[9], int n, const double Chat[3],
                                              double Dhat, const float gC[3], float gDr,
@@ -253,9 +255,9 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             float gsig = 0.f, gs[3] = {0.f, 0.f, 0.f};
             Sample s;
             if (work && sample_at(g, ray, k, s))
-                have = backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
+                have = backward_sample<POSE, VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
                                                    pa, idx, w, gsig, gs);
-            scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
+            scatter_merged<DEG>(have, s.base, idx, w, gsig, gs, Y, wc, grad);
             if (work) off = next_mark(marks, mark_last, off + 1);
         }
     } else if (GRID) {
@@ -289,9 +291,9 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             float w[8];
             float gsig = 0.f, gs[3] = {0.f, 0.f, 0.f};
             if (work)
-                have = backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
+                have = backward_sample<POSE, VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
                                                    pa, idx, w, gsig, gs);
-            scatter_merged(have, s.base, idx, w, gsig, gs, Y, wc, grad);
+            scatter_merged<DEG>(have, s.base, idx, w, gsig, gs, Y, wc, grad);
             ++k;
         }
     } else if (marks && !mark_overflow) {
@@ -303,7 +305,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             int idx[8];
             float w[8];
             float gsig, gs[3];
-            backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st, pa, idx, w,
+            backward_sample<POSE, VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st, pa, idx, w,
                                         gsig, gs);
         }
     } else {
@@ -325,7 +327,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             int idx[8];
             float w[8];
             float gsig, gs[3];
-            backward_sample<POSE, VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st, pa, idx, w,
+            backward_sample<POSE, VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st, pa, idx, w,
                                         gsig, gs);
             ++k;
         }
@@ -361,7 +363,7 @@ struct JacAcc {
 // One occupied sample of the Jacobian march: row k is the pose gradient of
 // output k alone (unit upstream on it), so the sample's factors are those of
 // Eq. 8-10 with gC = e_k (colour rows) or dL/d range = 1/s (depth row).
-template <bool VIEW>
+template <bool VIEW, int DEG>
 __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op, const Ray& ray,
                                                 const float Y[9], const float GY[9][3],
                                                 const Sample& s, const double Chat[3], double Dhat,
@@ -369,7 +371,7 @@ __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op,
     int idx[8];
     if (load_links(g, s.base, idx) == 0) return;
     Interp v;
-    gather_interp<true, VIEW>(g, idx, Y, GY, s.f, v);
+    gather_interp<true, VIEW, DEG>(g, idx, Y, GY, s.f, v);
     const float sr = v.sig;
     if (!(sr > 0.f)) return;
     const float delta = op.step_vox;
@@ -407,7 +409,7 @@ __device__ __forceinline__ void jacobian_sample(const KGrid& g, const KOpts& op,
 }
 
 // Jacobian rows J[k] = (g_o, o x g_o + d x g_d (+ d x g_view)) of one ray.
-template <bool VIEW>
+template <bool VIEW, int DEG>
 __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, const Ray& ray,
                                              const float Y[9], int n, const double Chat[3],
                                              double Dhat, float J[4][6],
@@ -427,7 +429,7 @@ __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, co
              off = next_mark(marks, mark_last, off + 1)) {
             Sample s;
             if (!sample_at(g, ray, ray.k_first + off, s)) break;
-            jacobian_sample<VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
+            jacobian_sample<VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
         }
     } else {
         int64_t k = ray.k_first;
@@ -445,7 +447,7 @@ __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, co
                     continue;
                 }
             }
-            jacobian_sample<VIEW>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
+            jacobian_sample<VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, st, ja);
             ++k;
         }
     }
@@ -469,6 +471,7 @@ __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, co
 // kernels
 // ---------------------------------------------------------------------------
 
+template <int DEG>
 __global__ void __launch_bounds__(256) k_forward(KGrid g, KRays rs, KOpts op, float* __restrict__ rgb,
                                                  float* __restrict__ depth, int32_t* __restrict__ nsamp) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -479,7 +482,7 @@ __global__ void __launch_bounds__(256) k_forward(KGrid g, KRays rs, KOpts op, fl
     float Y[9];
     sh9(ray.d[0], ray.d[1], ray.d[2], Y);
     FwdResult fr;
-    ray_forward(g, op, ray, Y, fr);
+    ray_forward<DEG>(g, op, ray, Y, fr);
     rgb[3 * r] = fr.C[0];
     rgb[3 * r + 1] = fr.C[1];
     rgb[3 * r + 2] = fr.C[2];
@@ -487,7 +490,7 @@ __global__ void __launch_bounds__(256) k_forward(KGrid g, KRays rs, KOpts op, fl
     nsamp[r] = fr.n;
 }
 
-template <bool GRID, bool POSE, bool VIEW>
+template <bool GRID, bool POSE, bool VIEW, int DEG>
 __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
                                                   const float* __restrict__ rgb,
                                                   const float* __restrict__ depth,
@@ -529,7 +532,7 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
             n = ray.empty ? 0 : nsamp[r];
         }
     }
-    ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, n, Chat, Dhat, gC, gDr, grad, wc, pa);
+    ray_backward<GRID, POSE, VIEW, DEG>(g, op, ray, Y, n, Chat, Dhat, gC, gDr, grad, wc, pa);
     if (POSE) {
         double six[6] = {0, 0, 0, 0, 0, 0};
         if (active) pose_six<VIEW>(ray, pa, six);
@@ -541,7 +544,7 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
 // PH 2: backward).  The forward launch needs no LDS and few registers, so it
 // runs at the occupancy of a forward-only kernel; it leaves each ray's work
 // mask and backward inputs in `sp`, from which the backward launch resumes.
-template <bool GRID, bool POSE, bool VIEW, int PH>
+template <bool GRID, bool POSE, bool VIEW, int PH, int DEG>
 __global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays rs, KOpts op,
                                                const float* __restrict__ tgt_rgb,
                                                const float* __restrict__ tgt_depth,
@@ -621,7 +624,7 @@ __global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays
             f = frame_of(rs.off, rs.F, r);
             setup_ray(g, rs, op, r, f, ray);
             sh9(ray.d[0], ray.d[1], ray.d[2], Y);
-            ray_forward(g, op, ray, Y, fr, marks, PH == 1 ? sp.n_pad : (int64_t)WAVE);
+            ray_forward<DEG>(g, op, ray, Y, fr, marks, PH == 1 ? sp.n_pad : (int64_t)WAVE);
             const float z = fr.D / ray.s;
             if (rgb_out) {
                 rgb_out[3 * r] = fr.C[0];
@@ -666,7 +669,7 @@ __global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays
             fr.Cd[0] = fr.Cd[1] = fr.Cd[2] = fr.Dd = 0.0;
         }
         if ((GRID || POSE) && PH != 1)
-            ray_backward<GRID, POSE, VIEW>(g, op, ray, Y, nb, fr.Cd, fr.Dd, gC, gDr, grad, wc, pa, marks,
+            ray_backward<GRID, POSE, VIEW, DEG>(g, op, ray, Y, nb, fr.Cd, fr.Dd, gC, gDr, grad, wc, pa, marks,
                                            fr.mark_last, fr.mark_overflow);
         if (loss && PH != 2) {
             double lv[1] = {lval};
@@ -698,7 +701,7 @@ __global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays
 // Gauss-Newton normal equations: per ray, forward, 4-residual and Jacobian;
 // per frame, H = sum w J^T W J (upper triangle), g = sum w J^T W e and the
 // error E, with W = diag(1, 1, 1, lambda_depth) over rays with a valid depth.
-template <bool VIEW>
+template <bool VIEW, int DEG>
 __global__ void __launch_bounds__(256) k_gn(KGrid g, KRays rs, KOpts op,
                                             const float* __restrict__ tgt_rgb,
                                             const float* __restrict__ tgt_depth,
@@ -720,14 +723,14 @@ __global__ void __launch_bounds__(256) k_gn(KGrid g, KRays rs, KOpts op,
         float Y[9];
         sh9(ray.d[0], ray.d[1], ray.d[2], Y);
         FwdResult fr;
-        ray_forward(g, op, ray, Y, fr, marks);
+        ray_forward<DEG>(g, op, ray, Y, fr, marks);
         const float Dt = tgt_depth[r];
         valid = isfinite(Dt) && Dt > 0.f;
         if (valid) {
             const float e[4] = {fr.C[0] - tgt_rgb[3 * r], fr.C[1] - tgt_rgb[3 * r + 1],
                                 fr.C[2] - tgt_rgb[3 * r + 2], fr.D / ray.s - Dt};
             float J[4][6];
-            ray_jacobian<VIEW>(g, op, ray, Y, fr.n, fr.Cd, fr.Dd, J, marks, fr.mark_last,
+            ray_jacobian<VIEW, DEG>(g, op, ray, Y, fr.n, fr.Cd, fr.Dd, J, marks, fr.mark_last,
                                fr.mark_overflow);
             const double wf = (double)fw[f];
             const double Wk[4] = {wf, wf, wf, wf * (double)op.lambda_d};
@@ -765,10 +768,20 @@ static inline unsigned blocks_for(int64_t n, int block) {
     return (unsigned)((n + block - 1) / block);
 }
 
+// Calls f(std::integral_constant<int, DEG>) for the grid's SH degree.
+template <class F>
+static void by_degree(int deg, F&& f) {
+    if (deg == 0) f(std::integral_constant<int, 0>{});
+    else if (deg == 1) f(std::integral_constant<int, 1>{});
+    else f(std::integral_constant<int, 2>{});
+}
+
 hipError_t launch_forward(const KGrid& g, const KRays& rs, const KOpts& op, float* rgb,
                           float* depth, int32_t* nsamp, hipStream_t st) {
-    hipLaunchKernelGGL(k_forward, dim3(blocks_for(rs.n, 256)), dim3(256), 0, st, g, rs, op, rgb,
-                       depth, nsamp);
+    by_degree(g.deg, [&](auto D) {
+        hipLaunchKernelGGL(k_forward<decltype(D)::value>, dim3(blocks_for(rs.n, 256)), dim3(256), 0, st,
+                           g, rs, op, rgb, depth, nsamp);
+    });
     return hipGetLastError();
 }
 
@@ -778,22 +791,23 @@ hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, con
                            hipStream_t st) {
     const dim3 grid(blocks_for(rs.n, 256)), block(256);
     const bool view = (op.flags & 1) != 0;
-    if (grad_data && !grad_pose) {
-        // one wave per workgroup: each wave stages its MFMA operands in ~19 KB of LDS
-        const size_t lds = WAVE_LDS_FLOATS * sizeof(float);
-        hipLaunchKernelGGL((k_backward<true, false, false>), dim3(blocks_for(rs.n, WAVE)),
-                           dim3(WAVE), lds, st, g, rs, op, rgb,
-                           depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
-    } else if (!grad_data && grad_pose) {
-        if (view)
-            hipLaunchKernelGGL((k_backward<false, true, true>), grid, block, 0, st, g, rs, op, rgb,
+    if (!((grad_data != nullptr) ^ (grad_pose != nullptr))) return hipErrorInvalidValue;
+    by_degree(g.deg, [&](auto D) {
+        constexpr int DEG = decltype(D)::value;
+        if (grad_data) {
+            // one wave per workgroup: each wave stages its MFMA operands in ~19 KB of LDS
+            const size_t lds = WAVE_LDS_FLOATS * sizeof(float);
+            hipLaunchKernelGGL((k_backward<true, false, false, DEG>), dim3(blocks_for(rs.n, WAVE)),
+                               dim3(WAVE), lds, st, g, rs, op, rgb, depth, nsamp, g_rgb, g_depth,
+                               grad_data, grad_pose);
+        } else if (view) {
+            hipLaunchKernelGGL((k_backward<false, true, true, DEG>), grid, block, 0, st, g, rs, op, rgb,
                                depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
-        else
-            hipLaunchKernelGGL((k_backward<false, true, false>), grid, block, 0, st, g, rs, op, rgb,
+        } else {
+            hipLaunchKernelGGL((k_backward<false, true, false, DEG>), grid, block, 0, st, g, rs, op, rgb,
                                depth, nsamp, g_rgb, g_depth, grad_data, grad_pose);
-    } else {
-        return hipErrorInvalidValue;
-    }
+        }
+    });
     return hipGetLastError();
 }
 
@@ -817,14 +831,14 @@ static int device_cus() {
 // kernel's register and LDS use), never more than there are tiles.
 // The per-CU figure is cached per kernel and block size; concurrent callers
 // may both compute it, and they store the same value.
-template <bool GRID, bool POSE, bool VIEW, int PH>
+template <bool GRID, bool POSE, bool VIEW, int PH, int DEG>
 static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
     static std::atomic<int> per_cu[4];                    // by block 64/128/256/512, 0 = unknown
     const int slot = block == 64 ? 0 : block == 128 ? 1 : block == 256 ? 2 : 3;
     int n = per_cu[slot].load(std::memory_order_relaxed);
     if (n <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW, PH>, block, lds)
-                != hipSuccess || n <= 0)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW, PH, DEG>, block,
+                                                         lds) != hipSuccess || n <= 0)
             n = 1;
         per_cu[slot].store(n, std::memory_order_relaxed);
     }
@@ -833,7 +847,7 @@ static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
     return (unsigned)(tiles < cap ? tiles : cap);
 }
 
-template <bool GRID, bool POSE, bool VIEW, int PH>
+template <bool GRID, bool POSE, bool VIEW, int PH, int DEG>
 static void fused_phase(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
                         const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                         const float* fw, float* rgb, float* depth, double* loss, float* grad,
@@ -841,29 +855,29 @@ static void fused_phase(int64_t tiles, dim3 block, hipStream_t st, const KGrid& 
     const size_t lds = PH == 1 ? 0
                      : GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float)
                      : POSE ? (block.x / WAVE) * MARK_WORDS * WAVE * sizeof(uint32_t) : 0;
-    const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW, PH>(block.x, lds, tiles)
+    const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW, PH, DEG>(block.x, lds, tiles)
                                : (unsigned)tiles);
-    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW, PH>), grid, block, lds, st, g, rs, op, tgt_rgb,
+    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW, PH, DEG>), grid, block, lds, st, g, rs, op, tgt_rgb,
                        tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent, sp);
 }
 
 // variant 0: one workgroup per tile; 1: persistent workgroups on the tile
 // queue; 2: a forward launch then a backward launch, both persistent, with
 // the per-ray state in the workspace
-template <bool GRID, bool POSE, bool VIEW>
+template <bool GRID, bool POSE, bool VIEW, int DEG>
 static void fused_go(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
                      const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                      const float* fw, float* rgb, float* depth, double* loss, float* grad,
                      double* gp, int64_t* stats, unsigned* ws, int variant) {
     if (variant == 2) {
         const KSplit sp = split_state(ws, rs.n);
-        fused_phase<GRID, POSE, VIEW, 1>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb, depth,
-                                         loss, grad, gp, stats, ws, 1, sp);
-        fused_phase<GRID, POSE, VIEW, 2>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb, depth,
-                                         loss, grad, gp, stats, ws, 1, sp);
+        fused_phase<GRID, POSE, VIEW, 1, DEG>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb,
+                                              depth, loss, grad, gp, stats, ws, 1, sp);
+        fused_phase<GRID, POSE, VIEW, 2, DEG>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb,
+                                              depth, loss, grad, gp, stats, ws, 1, sp);
     } else {
-        fused_phase<GRID, POSE, VIEW, 0>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb, depth,
-                                         loss, grad, gp, stats, ws, variant, KSplit{});
+        fused_phase<GRID, POSE, VIEW, 0, DEG>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb,
+                                              depth, loss, grad, gp, stats, ws, variant, KSplit{});
     }
 }
 
@@ -881,20 +895,22 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
     const int64_t tiles = (rs.n + block - 1) / block;
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;  // 32-bit grid and queue counters
     const dim3 blk(block);
-    const int64_t grid = tiles;
     const bool G = want & 1, P = want & 2, V = (op.flags & 1) != 0;
     int64_t* sp = (want & 4) ? stats : nullptr;
-    if (G && P) {
-        if (V) fused_go<true, true, true>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-        else fused_go<true, true, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-    } else if (G) {
-        fused_go<true, false, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-    } else if (P) {
-        if (V) fused_go<false, true, true>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-        else fused_go<false, true, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-    } else {
-        fused_go<false, false, false>(grid, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-    }
+    by_degree(g.deg, [&](auto D) {
+        constexpr int DEG = decltype(D)::value;
+        if (G && P) {
+            if (V) fused_go<true, true, true, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+            else fused_go<true, true, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+        } else if (G) {
+            fused_go<true, false, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+        } else if (P) {
+            if (V) fused_go<false, true, true, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+            else fused_go<false, true, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+        } else {
+            fused_go<false, false, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+        }
+    });
     return hipGetLastError();
 }
 
@@ -902,12 +918,15 @@ hipError_t launch_gn(const KGrid& g, const KRays& rs, const KOpts& op, const flo
                      const float* tgt_depth, const float* frame_weight, double* gn, hipStream_t st) {
     const dim3 grid(blocks_for(rs.n, 256)), block(256);
     const size_t lds = (256 / WAVE) * MARK_WORDS * WAVE * sizeof(uint32_t);
-    if (op.flags & 1)
-        hipLaunchKernelGGL((k_gn<true>), grid, block, lds, st, g, rs, op, tgt_rgb, tgt_depth,
-                           frame_weight, gn);
-    else
-        hipLaunchKernelGGL((k_gn<false>), grid, block, lds, st, g, rs, op, tgt_rgb, tgt_depth,
-                           frame_weight, gn);
+    by_degree(g.deg, [&](auto D) {
+        constexpr int DEG = decltype(D)::value;
+        if (op.flags & 1)
+            hipLaunchKernelGGL((k_gn<true, DEG>), grid, block, lds, st, g, rs, op, tgt_rgb, tgt_depth,
+                               frame_weight, gn);
+        else
+            hipLaunchKernelGGL((k_gn<false, DEG>), grid, block, lds, st, g, rs, op, tgt_rgb, tgt_depth,
+                               frame_weight, gn);
+    });
     return hipGetLastError();
 }
 

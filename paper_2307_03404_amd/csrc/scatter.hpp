@@ -79,11 +79,15 @@ constexpr int SMALL_PASS_LANES = 16;
 
 // Gradient of one sample: dL/d sigma_raw (gsig) and dL/ds_c (gs[c]) to be
 // spread over the corners of the cell with link base `key` (corner ids
-// idx[], trilinear weights w[]).  Must be reached by every lane of the wave.
+// idx[], trilinear weights w[]) in records of SH degree DEG (fields beyond
+// the record's used ones are staged as zeros and never written).  Must be
+// reached by every lane of the wave.
+template <int DEG>
 __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int idx[8],
                                                const float w[8], float gsig, const float gs[3],
                                                const float Y[9], const WaveStage& wc,
                                                float* __restrict__ grad) {
+    constexpr int NSH = RecL<DEG>::NSH, USED = RecL<DEG>::USED, S = RecL<DEG>::S;
     unsigned long long pending = __ballot(have);
     if (!pending) return;
     const int lane = lane_id();
@@ -92,12 +96,14 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
     // G rows, once per step (lanes without a gradient stage zeros)
     {
         float G[REC];
+#pragma unroll
+        for (int m = USED; m < REC; ++m) G[m] = 0.f;
         G[0] = have ? gsig : 0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float a = have ? gs[c] : 0.f;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) G[1 + 9 * c + k] = a * Y[k];
+            for (int k = 0; k < NSH; ++k) G[1 + NSH * c + k] = a * Y[k];
         }
 #pragma unroll
         for (int m = 0; m < REC; ++m) wc.sb[stage_at(m, lane)] = G[m];
@@ -174,7 +180,7 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
             const int id0 = __builtin_amdgcn_readlane(idx[r & 3], ld);
             const int id1 = __builtin_amdgcn_readlane(idx[4 + (r & 3)], ld);
             const int vid = h ? id1 : id0;
-            if (vid >= 0 && j < REC) unsafeAtomicAdd(grad + (int64_t)vid * REC + j, acc[r]);
+            if (vid >= 0 && j < USED) unsafeAtomicAdd(grad + (int64_t)vid * S + j, acc[r]);
         }
     }
 }

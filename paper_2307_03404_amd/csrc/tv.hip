@@ -12,9 +12,10 @@
 // sub-bricks.  The workgroup tests the block against the occupancy bitfield
 // once, loads the links of the block and its one-vertex halo (10^3) in one
 // pass, and then, for each sub-brick with an allocated vertex, stages the
-// sub-brick's 6^3 halo records with all 28 fields at once (each record read
-// as one contiguous 112-byte run) and computes its vertices' 28 fields with
-// 28 consecutive lanes, so each gradient record is written as one run.
+// sub-brick's 6^3 halo records with all their fields at once (each record
+// read as one contiguous run: 112 bytes at SH degree 2) and computes its
+// vertices' fields (28 at degree 2, 13 at degree 1, 4 at degree 0) with
+// consecutive lanes, so each gradient record is written as one run.
 // (Staging four fields at a time over 8^3 blocks fetched every record line
 // once per chunk, as the lines of ~200 blocks in flight per XCD do not
 // survive in L2 between chunks; one workgroup per 4^3 brick made the launch
@@ -37,16 +38,18 @@ constexpr int TH3 = TH * TH * TH;       // 216 staged positions
 constexpr int PLANE = TH3 + 1;          // padded field plane: lanes over fields hit distinct banks
 constexpr int TV_THREADS = 256;
 constexpr int TV_ITEMS = TB * TB * TB * 32 / TV_THREADS;   // vertex-field items per thread, at most
-constexpr int STAGE_ITERS = (TH3 * 7 + TV_THREADS - 1) / TV_THREADS;   // staged float4 per thread
 
 __device__ __forceinline__ int hidx8(int x, int y, int z) { return (x * TH8 + y) * TH8 + z; }
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (x * TH + y) * TH + z; }
 
+template <int DEG>
 __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float lam_sh, float eps,
                                                    float* __restrict__ grad, int nby, int nbz) {
+    constexpr int S = RecL<DEG>::S, Q = RecL<DEG>::Q, USED = RecL<DEG>::USED;
+    constexpr int STAGE_ITERS = (TH3 * Q + TV_THREADS - 1) / TV_THREADS;   // staged float4 per thread
     __shared__ int s_id8[TH83];             // links of the block halo (-1 empty or outside)
     __shared__ int s_id[TH3];               // links of the current sub-brick halo
-    __shared__ float s_v[REC][PLANE];       // field m of sub-halo position p at s_v[m][p]
+    __shared__ float s_v[S][PLANE];         // field m of sub-halo position p at s_v[m][p]
     __shared__ int s_list[TB * TB * TB];    // sub-halo positions of allocated sub-brick vertices
     __shared__ int s_n;
     const int t = threadIdx.x;
@@ -99,26 +102,26 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             __syncthreads();                                // s_n and s_list are rewritten next
             continue;
         }
-        // stage the sub-halo links and records: 7 lanes per position, one
+        // stage the sub-halo links and records: Q lanes per position, one
         // float4 each; all of a thread's loads are issued before its LDS writes
         float4 wv[STAGE_ITERS];
 #pragma unroll
         for (int k = 0; k < STAGE_ITERS; ++k) {
             const int i = t + k * TV_THREADS;
             wv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (i < TH3 * 7) {
-                const int p = i / 7, q = i - 7 * p;
+            if (i < TH3 * Q) {
+                const int p = i / Q, q = i - Q * p;
                 const int hx = p / (TH * TH), hy = (p / TH) % TH, hz = p % TH;
                 const int id = s_id8[hidx8(ox + hx, oy + hy, oz + hz)];
                 if (q == 0) s_id[p] = id;
-                if (id >= 0) wv[k] = reinterpret_cast<const float4*>(g.data + (int64_t)id * REC)[q];
+                if (id >= 0) wv[k] = reinterpret_cast<const float4*>(g.data + (int64_t)id * S)[q];
             }
         }
 #pragma unroll
         for (int k = 0; k < STAGE_ITERS; ++k) {
             const int i = t + k * TV_THREADS;
-            if (i < TH3 * 7) {
-                const int p = i / 7, q = i - 7 * p;
+            if (i < TH3 * Q) {
+                const int p = i / Q, q = i - Q * p;
                 s_v[4 * q][p] = wv[k].x;
                 s_v[4 * q + 1][p] = wv[k].y;
                 s_v[4 * q + 2][p] = wv[k].z;
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             }
         }
         __syncthreads();
-        // 32 lanes per allocated vertex, lane m < 28 takes field m.  A thread
+        // 32 lanes per allocated vertex, lane m < USED takes field m.  A thread
         // has at most TV_ITEMS items (n <= 64); their gradient entries are
         // read first, so the read-modify-writes cost one round trip, not one each.
         float gv[TV_ITEMS];
@@ -137,8 +140,8 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             const int m = it & 31;
             ga[k] = -1;
             gv[k] = 0.f;
-            if (it < n * 32 && m < REC) {
-                ga[k] = (int64_t)s_id[s_list[it >> 5]] * REC + m;
+            if (it < n * 32 && m < USED) {
+                ga[k] = (int64_t)s_id[s_list[it >> 5]] * S + m;
                 gv[k] = grad[ga[k]];
             }
         }
@@ -193,8 +196,15 @@ hipError_t launch_tv(const KGrid& g, float lambda_density, float lambda_sh, floa
     const int nbx = (g.R[0] + TB8 - 1) / TB8, nby = (g.R[1] + TB8 - 1) / TB8;
     const int nbz = (g.R[2] + TB8 - 1) / TB8;
     const int64_t nb = (int64_t)nbx * nby * nbz;
-    hipLaunchKernelGGL(k_tv, dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density, lambda_sh,
-                       eps, grad_data, nby, nbz);
+    if (g.deg == 0)
+        hipLaunchKernelGGL(k_tv<0>, dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
+                           lambda_sh, eps, grad_data, nby, nbz);
+    else if (g.deg == 1)
+        hipLaunchKernelGGL(k_tv<1>, dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
+                           lambda_sh, eps, grad_data, nby, nbz);
+    else
+        hipLaunchKernelGGL(k_tv<2>, dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
+                           lambda_sh, eps, grad_data, nby, nbz);
     return hipGetLastError();
 }
 

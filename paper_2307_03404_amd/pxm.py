@@ -17,7 +17,12 @@ import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpxm.so")
-REC = 28
+REC = 28                      # floats per record at SH degree 2
+
+
+def record_floats(sh_degree: int) -> int:
+    """Floats per vertex record of SH degree 0, 1 or 2 (PXM_RECORD_FLOATS)."""
+    return {0: 4, 1: 16, 2: 28}[int(sh_degree)]
 
 COLOR_RELU_SHIFT, COLOR_SIGMOID, COLOR_IDENTITY = 0, 1, 2
 DEPTH_L1, DEPTH_L2 = 0, 1
@@ -37,7 +42,7 @@ class PxmError(RuntimeError):
 class _Grid(C.Structure):
     _fields_ = [("reso", C.c_int32 * 3), ("aabb_min", C.c_float * 3), ("voxel_size", C.c_float),
                 ("link", C.c_void_p), ("n_alloc", C.c_int64), ("data", C.c_void_p),
-                ("occ", C.c_void_p)]
+                ("occ", C.c_void_p), ("sh_degree", C.c_int32)]
 
 
 class _Rays(C.Structure):
@@ -85,7 +90,7 @@ def lib():
         L.pxm_render_fused.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P, sz, P]
         L.pxm_render_fused_noalloc.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P]
         L.pxm_pose_adam.argtypes = [i32, P, P, P, f32, f32, f32, f32, P]
-        L.pxm_grid_rmsprop.argtypes = [i64, P, P, P, f32, f32, f32, f32, P]
+        L.pxm_grid_rmsprop.argtypes = [i64, i32, P, P, P, f32, f32, f32, f32, P]
         L.pxm_render_gn.argtypes = [G, R, O, P, P, P, P, P]
         L.pxm_pose_gn.argtypes = [i32, P, P, f32, P]
         L.pxm_grid_edit_workspace_bytes.argtypes = [G]
@@ -152,8 +157,9 @@ class DeviceGrid:
     aabb_min: tuple
     voxel_size: float
     link: torch.Tensor      # int32 [Rx*Ry*Rz]
-    data: torch.Tensor      # float32 [n_alloc, 28]
+    data: torch.Tensor      # float32 [n_alloc, record_floats(sh_degree)]
     occ: torch.Tensor = None  # int32 words of the occupancy bitfield (optional)
+    sh_degree: int = 2      # 2: nine SH coefficients per channel (the paper's); 1 or 0
 
     @property
     def n_alloc(self):
@@ -162,7 +168,7 @@ class DeviceGrid:
     def struct(self, data=None) -> _Grid:
         d = self.data if data is None else data
         _need(self.link, "grid.link", torch.int32, (int(np.prod(self.reso)),))
-        _need(d, "grid.data", torch.float32, (self.n_alloc, REC))
+        _need(d, "grid.data", torch.float32, (self.n_alloc, record_floats(self.sh_degree)))
         g = _Grid()
         g.reso[:] = [int(x) for x in self.reso]
         g.aabb_min[:] = [float(x) for x in self.aabb_min]
@@ -171,11 +177,13 @@ class DeviceGrid:
         g.n_alloc = self.n_alloc
         g.data = d.data_ptr()
         g.occ = self.occ.data_ptr() if self.occ is not None else None
+        g.sh_degree = int(self.sh_degree)
         return g
 
     def with_data(self, data) -> "DeviceGrid":
         """Same structure (links, occupancy) with another payload tensor."""
-        return DeviceGrid(self.reso, self.aabb_min, self.voxel_size, self.link, data, self.occ)
+        return DeviceGrid(self.reso, self.aabb_min, self.voxel_size, self.link, data, self.occ,
+                          self.sh_degree)
 
     def build_occupancy(self, stream=None) -> "DeviceGrid":
         """(Re)build the occupancy bitfield from the link table."""
@@ -237,7 +245,8 @@ def grid_to_device(grid, device="cuda", occupancy=True) -> DeviceGrid:
     g = DeviceGrid(tuple(int(r) for r in grid.reso), tuple(float(x) for x in grid.aabb_min),
                    float(grid.voxel_size),
                    torch.from_numpy(np.ascontiguousarray(grid.link, np.int32)).to(device),
-                   torch.from_numpy(np.ascontiguousarray(grid.data, np.float32)).to(device))
+                   torch.from_numpy(np.ascontiguousarray(grid.data, np.float32)).to(device),
+                   sh_degree=int(getattr(grid, "sh_degree", 2)))
     if occupancy:
         g.build_occupancy()
     return g
@@ -434,13 +443,15 @@ def gn_unpack(gn):
     return H, gn[:, 21:27], gn[:, 27]
 
 
-def grid_rmsprop(data, grad_data, state, lr_density, lr_sh, alpha=0.95, eps=1e-8, stream=None):
+def grid_rmsprop(data, grad_data, state, lr_density, lr_sh, alpha=0.95, eps=1e-8, stream=None,
+                 sh_degree=2):
     """Sparse RMSProp step on the vertex records (in place); zeroes grad_data."""
     n = int(data.shape[0])
-    _need(data, "data", torch.float32, (n, REC))
-    _need(grad_data, "grad_data", torch.float32, (n, REC))
-    _need(state, "state", torch.float32, (n, REC))
-    _check("grid_rmsprop", lib().pxm_grid_rmsprop(n, _ptr(data), _ptr(grad_data), _ptr(state),
+    S = record_floats(sh_degree)
+    _need(data, "data", torch.float32, (n, S))
+    _need(grad_data, "grad_data", torch.float32, (n, S))
+    _need(state, "state", torch.float32, (n, S))
+    _check("grid_rmsprop", lib().pxm_grid_rmsprop(n, int(sh_degree), _ptr(data), _ptr(grad_data), _ptr(state),
                                                   float(lr_density), float(lr_sh), float(alpha),
                                                   float(eps), _stream(stream)))
 
@@ -477,10 +488,12 @@ def grid_upsample(grid: DeviceGrid, ws=None, occupancy=True, stream=None) -> Dev
     reso, link, n = grid_upsample_link(grid, ws, stream)
     _sync(stream)
     n_fine = int(n.item())
-    data = torch.empty((n_fine, REC), dtype=torch.float32, device=grid.link.device)
+    data = torch.empty((n_fine, record_floats(grid.sh_degree)), dtype=torch.float32,
+                       device=grid.link.device)
     _check("grid_upsample_data", lib().pxm_grid_upsample_data(
         C.byref(grid.struct()), _ptr(link), n_fine, _ptr(data), _stream(stream)))
-    out = DeviceGrid(reso, grid.aabb_min, float(np.float32(grid.voxel_size) / np.float32(2)), link, data)
+    out = DeviceGrid(reso, grid.aabb_min, float(np.float32(grid.voxel_size) / np.float32(2)), link, data,
+                     sh_degree=grid.sh_degree)
     if occupancy:
         out.build_occupancy(stream)
     return out
@@ -500,7 +513,8 @@ def grid_prune(grid: DeviceGrid, tau: float, ws=None, in_place=False, occupancy=
     _check("grid_prune", lib().pxm_grid_prune(C.byref(g), float(tau), _ptr(link), _ptr(data), _ptr(n),
                                               _ptr(ws), ws.numel(), _stream(stream)))
     _sync(stream)
-    out = DeviceGrid(grid.reso, grid.aabb_min, grid.voxel_size, link, data[:int(n.item())])
+    out = DeviceGrid(grid.reso, grid.aabb_min, grid.voxel_size, link, data[:int(n.item())],
+                     sh_degree=grid.sh_degree)
     if occupancy:
         out.build_occupancy(stream)
     return out

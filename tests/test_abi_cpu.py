@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(pxm.EXPORTS) == set(names)
-    assert pxm.abi_version() == 5
+    assert pxm.abi_version() == 6
 
 
 def test_status_strings():
@@ -46,6 +46,7 @@ def good_grid():
     g.link = FAKE
     g.n_alloc = 10
     g.data = FAKE
+    g.sh_degree = 2
     return g
 
 
@@ -99,6 +100,8 @@ def fwd(g, r, o, outs=(FAKE, FAKE, FAKE)):
     (lambda g, r, o: setattr(o, "color_act", 3), 1),
     (lambda g, r, o: setattr(o, "depth_loss", 2), 1),
     (lambda g, r, o: setattr(o, "flags", 8), 1),
+    (lambda g, r, o: setattr(g, "sh_degree", 3), 1),
+    (lambda g, r, o: setattr(g, "sh_degree", -1), 1),
 ])
 def test_forward_rejects_bad_arguments(mutate, code):
     g, r, o = good_grid(), good_rays(), good_opts()
@@ -150,13 +153,15 @@ def test_tv_adam_and_tuning_checks():
     assert L.pxm_pose_adam(0, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.999, 1e-8, None) == 1
     assert L.pxm_pose_adam(2, FAKE, FAKE, FAKE, 1e-3, 1.0, 0.999, 1e-8, None) == 1
     assert L.pxm_pose_adam(2, FAKE, FAKE, None, 1e-3, 0.9, 0.999, 1e-8, None) == 1
-    assert L.pxm_grid_rmsprop(0, None, None, None, 0.1, 0.01, 0.9, 1e-8, None) == 0
-    assert L.pxm_grid_rmsprop(-1, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
-    assert L.pxm_grid_rmsprop(4, FAKE, FAKE, FAKE, 0.1, 0.01, 1.0, 1e-8, None) == 1
-    assert L.pxm_grid_rmsprop(4, FAKE, FAKE, FAKE, -0.1, 0.01, 0.9, 1e-8, None) == 1
-    assert L.pxm_grid_rmsprop(4, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 0.0, None) == 1
-    assert L.pxm_grid_rmsprop(4, FAKE, None, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
-    assert L.pxm_grid_rmsprop(4, FAKE + 4, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8,
+    assert L.pxm_grid_rmsprop(0, 2, None, None, None, 0.1, 0.01, 0.9, 1e-8, None) == 0
+    assert L.pxm_grid_rmsprop(-1, 2, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, 2, FAKE, FAKE, FAKE, 0.1, 0.01, 1.0, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, 2, FAKE, FAKE, FAKE, -0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, 2, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 0.0, None) == 1
+    assert L.pxm_grid_rmsprop(4, 2, FAKE, None, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, 3, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, -1, FAKE, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8, None) == 1
+    assert L.pxm_grid_rmsprop(4, 2, FAKE + 4, FAKE, FAKE, 0.1, 0.01, 0.9, 1e-8,
                               None) == 1
     assert L.pxm_set_tuning(100, 0) == 1
     assert L.pxm_set_tuning(256, 3) == 1
