@@ -1,8 +1,9 @@
 """Batching around the fused kernel: ray packer, autotuner, captured tracking loop.
 
 * pack_frames: many frames with uneven ray counts -> one CSR ray batch whose
-  rays are ordered in 8x8 pixel tiles inside each frame (one 64-lane wave per
-  tile), plus the permutation back to the caller's order.
+  rays are ordered inside each frame for coherent waves (8x8 pixel tiles for
+  a full frame, Z-order for a sparse subset; rayorder.py), plus the
+  permutation back to the caller's order.
 * Autotuner: times pxm_render_fused over launch shapes (rays per workgroup x
   plain/persistent tile queue) on the real inputs and caches the winner per
   problem signature in a JSON file.  Run it before any graph capture.
@@ -25,16 +26,7 @@ import numpy as np
 import torch
 
 from . import pxm
-
-
-def tile_sort(pix: np.ndarray, width: int, tile: int = 8) -> np.ndarray:
-    """Permutation putting pixels (u, v) in tile-major order (tiles row-major,
-    pixels row-major inside a tile)."""
-    pix = np.asarray(pix)
-    u, v = pix[:, 0].astype(np.int64), pix[:, 1].astype(np.int64)
-    tiles_x = (width + tile - 1) // tile
-    key = ((v // tile) * tiles_x + (u // tile)) * tile * tile + (v % tile) * tile + (u % tile)
-    return np.argsort(key, kind="stable")
+from .rayorder import frame_order, morton_sort, tile_sort  # noqa: F401 (re-exported)
 
 
 @dataclass
@@ -54,14 +46,18 @@ class PackedRays:
         return int(self.pix.shape[0])
 
 
-def pack_frames(frames, width: int, tile: int = 8) -> PackedRays:
-    """frames: iterable of (c2w [3,4], intr [4], pix [n_f, 2]).  Rays keep their
-    frame grouping (CSR); inside a frame they are reordered into pixel tiles."""
+def pack_frames(frames, width: int, tile: int = 8, height: int | None = None) -> PackedRays:
+    """frames: iterable of (c2w [3,4], intr [4], pix [n_f, 2]) of images
+    `width` x `height` pixels (height defaults to the largest v + 1 seen).
+    Rays keep their frame grouping (CSR); inside a frame they are reordered
+    for coherent waves (rayorder.frame_order)."""
+    frames = [(m, k, np.asarray(p, np.int32).reshape(-1, 2)) for m, k, p in frames]
+    if height is None:
+        height = max([int(p[:, 1].max()) + 1 for _, _, p in frames if p.shape[0]] or [1])
     c2w, intr, pix, order, counts = [], [], [], [], []
     base = 0
     for m, k, p in frames:
-        p = np.asarray(p, np.int32).reshape(-1, 2)
-        perm = tile_sort(p, width, tile)
+        perm = frame_order(p, width, height, tile)
         c2w.append(np.asarray(m, np.float32).reshape(3, 4))
         intr.append(np.asarray(k, np.float32).reshape(4))
         pix.append(p[perm])

@@ -196,9 +196,12 @@ def tile_order(width: int, height: int, tile: int = 8) -> np.ndarray:
 
 
 def subsample_pixels(width, height, n, rng) -> np.ndarray:
-    """n distinct pixels, uniform without replacement, sorted by pixel index."""
+    """n distinct pixels, uniform without replacement, in the batch order of
+    a sparse subset (Z-order of (u, v); see rayorder.py)."""
+    from .rayorder import morton_sort
     flat = np.sort(rng.choice(width * height, size=n, replace=False))
-    return np.stack([flat % width, flat // width], 1).astype(np.int32)
+    pix = np.stack([flat % width, flat // width], 1).astype(np.int32)
+    return pix[morton_sort(pix)]
 
 
 # ----------------------------------------------------------------------------

@@ -20,6 +20,35 @@ def test_tile_sort_groups_8x8_blocks():
     np.testing.assert_array_equal(full[tile_sort(full, 1200)], full)
 
 
+def test_morton_sort_is_a_z_curve():
+    from paper_2307_03404_amd.rayorder import morton_sort
+    v, u = np.mgrid[0:64, 0:64]
+    pix = np.stack([u.ravel(), v.ravel()], 1)
+    p = pix[morton_sort(pix)]
+    # every aligned 2^k x 2^k block is one contiguous run, blocks in Z order
+    for k in (1, 3, 5):
+        blk = (p[:, 1] >> k) * (64 >> k) + (p[:, 0] >> k)
+        runs = blk[np.r_[True, np.diff(blk) != 0]]
+        assert len(runs) == (64 >> k) ** 2 and len(set(runs.tolist())) == len(runs)
+    np.testing.assert_array_equal(p[:4], [[0, 0], [1, 0], [0, 1], [1, 1]])
+    # on a sparse subset, 64 consecutive rays stay in a compact patch
+    rng = np.random.default_rng(3)
+    sub = synth.subsample_pixels(1200, 680, 100000, rng)
+    spans = [np.ptp(sub[i:i + 64], axis=0).max() for i in range(0, 100000 - 64, 64)]
+    assert np.median(spans) < 64
+    flat = sub[:, 1] * 1200 + sub[:, 0]
+    assert len(np.unique(flat)) == 100000
+
+
+def test_frame_order_tiles_full_frames_and_z_orders_subsets():
+    from paper_2307_03404_amd.rayorder import frame_order, morton_sort, tile_sort
+    full = synth.tile_order(1200, 680)
+    np.testing.assert_array_equal(frame_order(full, 1200, 680), tile_sort(full, 1200))
+    rng = np.random.default_rng(4)
+    sub = synth.subsample_pixels(1200, 680, 3000, rng)
+    np.testing.assert_array_equal(frame_order(sub, 1200, 680), morton_sort(sub))
+
+
 def test_pack_frames_csr_and_inverse_order():
     rng = np.random.default_rng(1)
     frames = []

@@ -30,21 +30,37 @@ def _profile(tmp_path, sha, workload="wl", block=64, variant=1, traffic="123456"
     p = tmp_path / "traffic.md"
     p.write_text("# counters\n\n"
                  f"- workload: `{workload}`\n- block: `{block}`\n- variant: `{variant}`\n"
-                 f"- sources_sha256: `{sha}`\n- traffic_bytes_per_launch: `{traffic}`\n")
-    return str(p)
+                 f"- sources_sha256: `{sha}`\n- traffic_bytes_per_launch: `{traffic}`\n"
+                 "- fetch_kib_per_launch: `10`\n- write_kib_per_launch: `100`\n"
+                 "- fetch_scale: `0.5`\n- write_scale: `1.0`\n")
+    return p.name
 
 
 def test_traffic_only_for_matching_sources_workload_and_launch(tmp_path, monkeypatch):
     sha = bench.sources_sha256()
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, sha))
-    assert bench.measured_traffic("wl", 64, 1) == 123456.0
+    monkeypatch.setattr(bench, "PROFILES_DIR", str(tmp_path))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILES", {"wl": _profile(tmp_path, sha),
+                                                    "other": "missing.md"})
+    t = bench.measured_traffic("wl", 64, 1)
+    assert t["bytes"] == 123456.0 and t["read_bytes"] == 20 * 1024 and t["write_bytes"] == 100 * 1024
     assert bench.measured_traffic("other", 64, 1) is None
+    assert bench.measured_traffic("unknown", 64, 1) is None
     assert bench.measured_traffic("wl", 128, 1) is None
     assert bench.measured_traffic("wl", 64, 0) is None
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, "0" * 64))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILES", {"wl": _profile(tmp_path, "0" * 64)})
     assert bench.measured_traffic("wl", 64, 1) is None
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
-    assert bench.measured_traffic("wl", 64, 1) is None
+
+
+def test_roofline_fraction_is_measured_traffic_over_peak():
+    tr = {"bytes": 2.0e9, "read_bytes": 0.5e9, "write_bytes": 1.5e9}
+    r = bench.roofline(40.0e9, 0.25e9, 4.0, tr, "k", "c2_room256_1200x680_mapping")
+    assert r["bound"] == "latency" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["achieved"] == pytest.approx(500.0) and r["frac"] == pytest.approx(500.0 / 8000.0)
+    assert r["frac"] <= 1.0 and r["traffic"] == 2.0e9
+    assert r["traffic_over_compulsory"] == pytest.approx(8.0)
+    assert r["gather_issue"]["gbs"] == pytest.approx(10000.0)
+    none = bench.roofline(40.0e9, 0.25e9, 4.0, None, "k", "c2_room256_1200x680_mapping")
+    assert none["achieved"] is None and none["frac"] is None and none["traffic"] is None
 
 
 def test_sources_digest_covers_the_kernel_sources():
