@@ -95,8 +95,9 @@ typedef struct {
                                NULL when n_alloc == 0, as may every grad_data argument (grad_data
                                arrays have the same layout as data) */
     const uint32_t *occ;    /* optional occupancy bitfield from pxm_build_occupancy for THIS
-                               link table, or NULL.  Lets the march step over empty cells and
-                               8^3-cell bricks; results are identical with or without it. */
+                               link table (8-byte aligned), or NULL.  Lets the march step over
+                               empty cells, 4^3-cell blocks and 8^3-cell bricks; results are
+                               identical with or without it. */
     int32_t sh_degree;      /* SH degree of the records: 2 (the paper's), 1 or 0 */
 } pxm_grid;
 
@@ -268,11 +269,14 @@ int pxm_grid_rmsprop(int64_t n_alloc, int32_t sh_degree, float *data, float *gra
 /*
  * Occupancy bitfield for empty-space skipping (an exact acceleration: a cell
  * whose 8 corners are all empty interpolates to zero density and carries no
- * light or gradient).  Level 0 holds one bit per cell ((x*(Ry-1)+y)*W0 + z/32,
- * W0 = ceil((Rz-1)/32)), level 1 one bit per brick of 8^3 cells.  Build it on
- * `stream` from grid->link / grid->n_alloc (grid->data and grid->occ are not
- * read) into `occ` of n_words >= pxm_occupancy_words(grid) uint32 words, and
- * rebuild it whenever the link table changes.
+ * light or gradient).  Level 0 holds one 64-bit word per block of 4^3 cells,
+ * block (qx, qy, qz) at (qx*Qy + qy)*Qz + qz with Q = ceil((R-1)/4) per axis,
+ * cell (x, y, z) at bit (x&3)*16 + (y&3)*4 + (z&3) of its block's word
+ * (little-endian: the low half is the first of two uint32 words).  Level 1,
+ * after level 0, holds one bit per brick of 8^3 cells.  Build it on `stream`
+ * from grid->link / grid->n_alloc (grid->data and grid->occ are not read) into
+ * `occ` (8-byte aligned) of n_words >= pxm_occupancy_words(grid) uint32 words,
+ * and rebuild it whenever the link table changes.
  */
 size_t pxm_occupancy_words(const pxm_grid *grid);
 int pxm_build_occupancy(const pxm_grid *grid, uint32_t *occ, size_t n_words, void *stream);

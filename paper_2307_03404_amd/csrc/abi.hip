@@ -49,6 +49,8 @@ int check_grid(const pxm_grid* g, bool need_payload = true) {
         return fail(PXM_INVALID_ARGUMENT, "grid.data is NULL");
     if (g->data && (reinterpret_cast<uintptr_t>(g->data) & 15))
         return fail(PXM_INVALID_ARGUMENT, "grid.data must be 16-byte aligned");
+    if (g->occ && (reinterpret_cast<uintptr_t>(g->occ) & 7))
+        return fail(PXM_INVALID_ARGUMENT, "grid.occ must be 8-byte aligned");
     return PXM_OK;
 }
 
@@ -92,8 +94,8 @@ pxm::KGrid kgrid(const pxm_grid* g) {
     k.link = g->link;
     k.data = g->data;
     int64_t w0, w1;
-    pxm::occ_layout(g->reso, w0, k.W0, k.B, w1);
-    k.occ0 = g->occ;
+    pxm::occ_layout(g->reso, w0, k.Q, k.B, w1);
+    k.occ0 = reinterpret_cast<const uint64_t*>(g->occ);
     k.occ1 = g->occ ? g->occ + w0 : nullptr;
     return k;
 }
@@ -228,18 +230,20 @@ int pxm_tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, flo
 size_t pxm_occupancy_words(const pxm_grid* grid) {
     if (check_grid(grid, false) != PXM_OK) return 0;
     int64_t w0, w1;
-    int W0, B[3];
-    pxm::occ_layout(grid->reso, w0, W0, B, w1);
+    int Q[3], B[3];
+    pxm::occ_layout(grid->reso, w0, Q, B, w1);
     return (size_t)(w0 + w1);
 }
 
 int pxm_build_occupancy(const pxm_grid* grid, uint32_t* occ, size_t n_words, void* stream) {
     PXM_TRY(check_grid(grid, false));
     if (!occ) return fail(PXM_INVALID_ARGUMENT, "occ is NULL");
+    if (reinterpret_cast<uintptr_t>(occ) & 7) return fail(PXM_INVALID_ARGUMENT, "occ must be 8-byte aligned");
     const size_t need = pxm_occupancy_words(grid);
     if (n_words < need) return fail(PXM_WORKSPACE_TOO_SMALL, "occ has %zu < %zu words", n_words, need);
     pxm::KGrid k = kgrid(grid);
-    k.occ0 = k.occ1 = nullptr;
+    k.occ0 = nullptr;
+    k.occ1 = nullptr;
     return launched(pxm::launch_occupancy(k, occ, (hipStream_t)stream), "build_occupancy");
 }
 

@@ -63,9 +63,10 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
 hipError_t launch_tv(const KGrid& g, float lambda_density, float lambda_sh, float eps,
                      float* grad_data, hipStream_t st);
 
-// Occupancy bitfield: level-0 words, words per cell row, bricks per axis,
-// level-1 words for a lattice of R vertices per axis.
-void occ_layout(const int R[3], int64_t& w0_words, int& W0, int B[3], int64_t& w1_words);
+// Occupancy bitfield: level-0 32-bit words (two per 4^3-cell block), 4^3
+// blocks per axis, 8^3 bricks per axis, level-1 words for a lattice of R
+// vertices per axis.
+void occ_layout(const int R[3], int64_t& w0_words, int Q[3], int B[3], int64_t& w1_words);
 hipError_t launch_occupancy(const KGrid& g, uint32_t* occ, hipStream_t st);
 
 hipError_t launch_adam(int F, float* c2w, double* grad_pose, double* state, float lr, float b1,

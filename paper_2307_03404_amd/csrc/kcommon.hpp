@@ -57,9 +57,9 @@ struct KGrid {
     const int32_t* __restrict__ link;
     const float* __restrict__ data;
     // optional occupancy bitfield (see occ.hip); occ0 == nullptr disables skipping
-    const uint32_t* __restrict__ occ0;   // one bit per cell, rows along z
+    const uint64_t* __restrict__ occ0;   // one 64-bit word per 4^3-cell block, a bit per cell
     const uint32_t* __restrict__ occ1;   // one bit per 8^3-cell brick
-    int W0;                              // level-0 words per (x, y) cell row
+    int Q[3];                            // 4^3 blocks per axis
     int B[3];                            // bricks per axis
 };
 
@@ -332,34 +332,80 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
 // empty-space skipping with the occupancy bitfield
 // ---------------------------------------------------------------------------
 
-// A cell is occupied iff one of its 8 corners is allocated.
-__device__ __forceinline__ bool cell_occupied(const KGrid& g, const int c[3]) {
-    const uint32_t w = g.occ0[((int64_t)c[0] * (g.R[1] - 1) + c[1]) * g.W0 + (c[2] >> 5)];
-    return (w >> (c[2] & 31)) & 1u;
-}
-
+// A cell is occupied iff one of its 8 corners is allocated.  Level 1 holds a
+// bit per 8^3-cell brick; level 0 a 64-bit word per 4^3-cell block, bit
+// (x & 3) * 16 + (y & 3) * 4 + (z & 3) for cell (x, y, z).
 __device__ __forceinline__ bool brick_empty(const KGrid& g, const int c[3]) {
     const int64_t b = ((int64_t)(c[0] >> 3) * g.B[1] + (c[1] >> 3)) * g.B[2] + (c[2] >> 3);
     return !((g.occ1[b >> 5] >> (b & 31)) & 1u);
 }
 
-// For sample k lying in an empty brick: the first sample index after k that is
-// not guaranteed to lie inside the brick.  Every index in (k, result) has its
-// position inside [8b, min(8b + 8, R - 1)) shrunk by 1e-6 voxel on each axis,
-// hence in one of the brick's (empty) cells and inside the box.
-__device__ __forceinline__ int64_t brick_exit(const KGrid& g, const Ray& ray, int64_t k,
+// For sample k lying in an empty block of E^3 cells (E = 8: a brick, E = 4:
+// a level-0 block): the first sample index after k that is not guaranteed
+// to lie inside the block.  Every index in (k, result) has its position
+// inside [E b, min(E b + E, R - 1)) shrunk by 1e-6 voxel on each axis, hence
+// in one of the block's (empty) cells and inside the box.
+template <int E>
+__device__ __forceinline__ int64_t block_exit(const KGrid& g, const Ray& ray, int64_t k,
                                               const int c[3]) {
     double kx = 1.0e300;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double lo = (double)(8 * (c[a] >> 3));
-        const double hi = fmin(lo + 8.0, (double)(g.R[a] - 1));
+        const double lo = (double)(E * (c[a] / E));
+        const double hi = fmin(lo + (double)E, (double)(g.R[a] - 1));
         if (ray.st[a] > 0.0) kx = fmin(kx, (hi - 1e-6 - ray.b[a]) / ray.st[a]);
         else if (ray.st[a] < 0.0) kx = fmin(kx, (lo + 1e-6 - ray.b[a]) / ray.st[a]);
     }
     if (!(kx < 4.0e18)) return k + 1;
     const int64_t nxt = (int64_t)floor(kx) + 1;
     return nxt > k + 1 ? nxt : k + 1;
+}
+
+// The brick and level-0 block a march is in, and their occupancy: a sample
+// loads a word only when it enters another brick or block (a ray crosses
+// ~13 blocks of 4^3 cells in the ~70 samples it takes through non-empty
+// bricks of the room frame).
+struct OccCache {
+    int brick;          // linear brick id, -1 = none yet
+    int blk;            // linear level-0 block id, -1 = none yet
+    bool brick_empty;
+    uint64_t word;
+};
+
+__device__ __forceinline__ void occ_cache_init(OccCache& oc) {
+    oc.brick = -1;
+    oc.blk = -1;
+    oc.brick_empty = false;
+    oc.word = 0ull;
+}
+
+enum { OCC_CELL = 0, OCC_EMPTY_CELL = 1, OCC_JUMP = 2 };
+
+// What the march does at sample k (inside the box, cell s.c): work at an
+// occupied cell, step over one empty cell, or jump to *nxt over an empty
+// brick or level-0 block.  Needs g.occ0 != nullptr.
+__device__ __forceinline__ int occ_classify(const KGrid& g, const Ray& ray, int64_t k,
+                                            const int c[3], OccCache& oc, int64_t& nxt) {
+    const int bid = ((c[0] >> 3) * g.B[1] + (c[1] >> 3)) * g.B[2] + (c[2] >> 3);
+    if (bid != oc.brick) {
+        oc.brick = bid;
+        oc.brick_empty = !((g.occ1[bid >> 5] >> (bid & 31)) & 1u);
+    }
+    if (oc.brick_empty) {
+        nxt = block_exit<8>(g, ray, k, c);
+        return OCC_JUMP;
+    }
+    const int qid = ((c[0] >> 2) * g.Q[1] + (c[1] >> 2)) * g.Q[2] + (c[2] >> 2);
+    if (qid != oc.blk) {
+        oc.blk = qid;
+        oc.word = g.occ0[qid];
+    }
+    if (oc.word == 0ull) {
+        nxt = block_exit<4>(g, ray, k, c);
+        return OCC_JUMP;
+    }
+    const int bit = ((c[0] & 3) << 4) | ((c[1] & 3) << 2) | (c[2] & 3);
+    return ((oc.word >> bit) & 1ull) ? OCC_CELL : OCC_EMPTY_CELL;
 }
 
 // Corner b = 4*i + 2*j + k  (x, y, z offsets in {0,1}).

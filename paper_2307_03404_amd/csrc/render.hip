@@ -62,12 +62,15 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
     if (!ray.empty) {
         const float delta = op.step_vox;
         int64_t k = ray.k_first;
+        OccCache oc;
+        occ_cache_init(oc);
         while (n < op.max_samples) {
             Sample s;
             if (!sample_at(g, ray, k, s)) break;
             if (g.occ0) {
-                if (brick_empty(g, s.c)) {
-                    const int64_t nxt = brick_exit(g, ray, k, s.c);
+                int64_t nxt;
+                const int cls = occ_classify(g, ray, k, s.c, oc, nxt);
+                if (cls == OCC_JUMP) {
                     if (nxt - k >= (int64_t)(op.max_samples - n)) {
                         n = op.max_samples;
                         break;
@@ -76,7 +79,7 @@ __device__ __forceinline__ void ray_forward(const KGrid& g, const KOpts& op, con
                     k = nxt;
                     continue;
                 }
-                if (!cell_occupied(g, s.c)) {
+                if (cls == OCC_EMPTY_CELL) {
                     ++n;
                     ++k;
                     continue;
@@ -262,6 +265,8 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
         }
     } else if (GRID) {
         int64_t k = wave_min(has ? ks : INT64_MAX);
+        OccCache oc;
+        occ_cache_init(oc);
         for (;;) {
             const bool live = has && k < ke;
             if (__ballot(live) == 0) break;
@@ -273,11 +278,13 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
                 if (!sample_at(g, ray, k, s)) {
                     has = false;            // left the box: nothing further on this ray
                     adv = INT64_MAX;
-                } else if (g.occ0 && brick_empty(g, s.c)) {
-                    const int64_t nxt = brick_exit(g, ray, k, s.c);
-                    adv = (nxt < ke ? nxt : ke) - k;
-                } else if (!g.occ0 || cell_occupied(g, s.c)) {
+                } else if (!g.occ0) {
                     work = true;
+                } else {
+                    int64_t nxt;
+                    const int cls = occ_classify(g, ray, k, s.c, oc, nxt);
+                    if (cls == OCC_JUMP) adv = (nxt < ke ? nxt : ke) - k;
+                    else work = cls == OCC_CELL;
                 }
             }
             if (__ballot(work) == 0) {
@@ -310,16 +317,19 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
         }
     } else {
         int64_t k = ks;
+        OccCache oc;
+        occ_cache_init(oc);
         while (k < ke) {
             Sample s;
             if (!sample_at(g, ray, k, s)) break;
             if (g.occ0) {
-                if (brick_empty(g, s.c)) {
-                    const int64_t nxt = brick_exit(g, ray, k, s.c);
+                int64_t nxt;
+                const int cls = occ_classify(g, ray, k, s.c, oc, nxt);
+                if (cls == OCC_JUMP) {
                     k = nxt < ke ? nxt : ke;
                     continue;
                 }
-                if (!cell_occupied(g, s.c)) {
+                if (cls == OCC_EMPTY_CELL) {
                     ++k;
                     continue;
                 }
@@ -433,16 +443,19 @@ __device__ __forceinline__ void ray_jacobian(const KGrid& g, const KOpts& op, co
         }
     } else {
         int64_t k = ray.k_first;
+        OccCache oc;
+        occ_cache_init(oc);
         while (k < ke) {
             Sample s;
             if (!sample_at(g, ray, k, s)) break;
             if (g.occ0) {
-                if (brick_empty(g, s.c)) {
-                    const int64_t nxt = brick_exit(g, ray, k, s.c);
+                int64_t nxt;
+                const int cls = occ_classify(g, ray, k, s.c, oc, nxt);
+                if (cls == OCC_JUMP) {
                     k = nxt < ke ? nxt : ke;
                     continue;
                 }
-                if (!cell_occupied(g, s.c)) {
+                if (cls == OCC_EMPTY_CELL) {
                     ++k;
                     continue;
                 }

@@ -314,10 +314,13 @@ def _occupancy_numpy(grid):
         for j in (0, 1):
             for k in (0, 1):
                 cell |= L[i:R[0] - 1 + i, j:R[1] - 1 + j, k:R[2] - 1 + k]
-    W0 = (R[2] - 1 + 31) // 32
-    pad = np.zeros((R[0] - 1, R[1] - 1, W0 * 32), bool)
-    pad[:, :, :R[2] - 1] = cell
-    w0 = np.packbits(pad.reshape(-1, 32)[:, ::-1], axis=1).view(">u4").ravel().astype(np.uint32)
+    # level 0: a 64-bit word per 4^3 block, bit (x&3)*16 + (y&3)*4 + (z&3)
+    Q = (R - 1 + 3) // 4
+    qpad = np.zeros(tuple(Q * 4), bool)
+    qpad[:R[0] - 1, :R[1] - 1, :R[2] - 1] = cell
+    blocks = qpad.reshape(Q[0], 4, Q[1], 4, Q[2], 4).transpose(0, 2, 4, 1, 3, 5).reshape(-1, 64)
+    words = (blocks.astype(np.uint64) << np.arange(64, dtype=np.uint64)).sum(axis=1, dtype=np.uint64)
+    w0 = words.view(np.uint32)                  # little-endian: low half first
     B = (R - 1 + 7) // 8
     bpad = np.zeros(tuple(B * 8), bool)
     bpad[:R[0] - 1, :R[1] - 1, :R[2] - 1] = cell
