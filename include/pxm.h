@@ -83,7 +83,9 @@ enum { PXM_FLAG_POSE_VIEWDIR = 1 };  /* add the exact d(colour)/d(view direction
 /* pxm_render_fused `want` bits */
 enum { PXM_WANT_GRID = 1,    /* accumulate grad_data */
        PXM_WANT_POSE = 2,    /* accumulate grad_pose */
-       PXM_WANT_STATS = 4 }; /* accumulate the traffic counters into `stats` */
+       PXM_WANT_STATS = 4,   /* accumulate the traffic counters into `stats` */
+       PXM_WANT_DETERMINISTIC = 8 };  /* with PXM_WANT_GRID: order-independent grid gradient
+                                         (a debug and race-detection mode; see pxm_render_fused) */
 
 typedef struct {
     int32_t reso[3];        /* vertices per axis, each >= 2 */
@@ -200,6 +202,16 @@ int pxm_tv_grad(const pxm_grid *grid, float lambda_density, float lambda_sh, flo
  *   The counters must be zeroed before the first use; every call leaves them
  *   zeroed again (the per-ray state needs no initialisation).  Calls that
  *   share one workspace must not run concurrently.
+ * PXM_WANT_DETERMINISTIC (with PXM_WANT_GRID): each merged grid-gradient
+ *   contribution is rounded to a fixed-point integer (units of 2^-48) and
+ *   summed with 64-bit integer atomics, which commute exactly; a last pass
+ *   adds every integer sum, converted once, into grad_data.  The result is
+ *   bit-for-bit the same whatever the order in which waves run, the launch
+ *   tuning or the run; it differs from the float-atomic result by rounding
+ *   only (each contribution within 2^-49, each entry within +-32768).  The
+ *   workspace then also holds the [n_alloc][S] int64 fixed-point buffer
+ *   (pxm_workspace_bytes with the same `want`), which must be zeroed before
+ *   the first use and is left zeroed.
  */
 int pxm_render_fused(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
                      const float *tgt_rgb, const float *tgt_depth, const float *frame_weight,
@@ -362,7 +374,8 @@ int pxm_render_fused_noalloc(const pxm_grid *grid, const pxm_rays *rays, const p
                              void *stream);
 
 /* Workspace bytes pxm_render_fused needs for these arguments and `want`, under
- * any launch tuning: 256 + 184 * (n_rays rounded up to 64). */
+ * any launch tuning: 256 + 184 * (n_rays rounded up to 64), plus, with
+ * PXM_WANT_GRID | PXM_WANT_DETERMINISTIC, 8 * n_alloc * S rounded up to 256. */
 size_t pxm_workspace_bytes(const pxm_grid *grid, const pxm_rays *rays, const pxm_opts *opts,
                            int32_t want);
 

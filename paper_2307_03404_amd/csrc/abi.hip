@@ -249,8 +249,12 @@ int pxm_build_occupancy(const pxm_grid* grid, uint32_t* occ, size_t n_words, voi
 
 size_t pxm_workspace_bytes(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
                            int32_t want) {
-    (void)grid; (void)opts; (void)want;
-    return pxm::fused_workspace_bytes(rays && rays->n_rays > 0 ? rays->n_rays : 0);
+    (void)opts;
+    size_t b = pxm::fused_workspace_bytes(rays && rays->n_rays > 0 ? rays->n_rays : 0);
+    if ((want & PXM_WANT_DETERMINISTIC) && (want & PXM_WANT_GRID) && grid && grid->n_alloc > 0 &&
+        grid->sh_degree >= 0 && grid->sh_degree <= 2)
+        b += pxm::fix_bytes(grid->n_alloc, PXM_RECORD_FLOATS(grid->sh_degree));
+    return b;
 }
 
 int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts* opts,
@@ -260,7 +264,7 @@ int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts*
     PXM_TRY(check_grid(grid));
     PXM_TRY(check_rays(rays));
     PXM_TRY(check_opts(opts));
-    if (want & ~(PXM_WANT_GRID | PXM_WANT_POSE | PXM_WANT_STATS))
+    if (want & ~(PXM_WANT_GRID | PXM_WANT_POSE | PXM_WANT_STATS | PXM_WANT_DETERMINISTIC))
         return fail(PXM_INVALID_ARGUMENT, "unknown want bits 0x%x", want);
     if (rays->n_rays > 0 && (!tgt_rgb || !tgt_depth || !frame_weight))
         return fail(PXM_INVALID_ARGUMENT, "targets / frame_weight is NULL");
@@ -275,9 +279,13 @@ int pxm_render_fused(const pxm_grid* grid, const pxm_rays* rays, const pxm_opts*
     if (rays->n_rays == 0) return PXM_OK;
     const int32_t tune = g_tuning.load();
     const int block = tune_block(tune), variant = tune_variant(tune);
+    unsigned long long* gfix = nullptr;
+    if ((want & PXM_WANT_DETERMINISTIC) && (want & PXM_WANT_GRID) && grid->n_alloc > 0)
+        gfix = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) +
+                                                     pxm::fused_workspace_bytes(rays->n_rays));
     return launched(pxm::launch_fused(kgrid(grid), krays(rays), kopts(opts), tgt_rgb, tgt_depth,
                                       frame_weight, want, rgb, depth, loss, grad_data, grad_pose,
-                                      stats, reinterpret_cast<unsigned*>(ws), block, variant,
+                                      stats, reinterpret_cast<unsigned*>(ws), block, variant, gfix,
                                       (hipStream_t)stream), "render_fused");
 }
 
@@ -470,6 +478,8 @@ int pxm_render_fused_noalloc(const pxm_grid* grid, const pxm_rays* rays, const p
     PXM_TRY(check_grid(grid));
     PXM_TRY(check_rays(rays));
     PXM_TRY(check_opts(opts));
+    if (want & PXM_WANT_DETERMINISTIC)
+        return fail(PXM_UNSUPPORTED, "the deterministic scatter needs a workspace: use pxm_render_fused");
     if (want & ~(PXM_WANT_GRID | PXM_WANT_POSE | PXM_WANT_STATS))
         return fail(PXM_INVALID_ARGUMENT, "unknown want bits 0x%x", want);
     if (rays->n_rays > 0 && (!tgt_rgb || !tgt_depth || !frame_weight))
@@ -500,7 +510,7 @@ int pxm_render_fused_noalloc(const pxm_grid* grid, const pxm_rays* rays, const p
     PXM_TRY(launched(hipGetLastError(), "render_fused_noalloc (clear)"));
     return launched(pxm::launch_fused(kgrid(grid), krays(rays), kopts(opts), tgt_rgb, tgt_depth,
                                       frame_weight, want, rgb, depth, loss, grad_data, grad_pose,
-                                      stats, counters, block, variant, st),
+                                      stats, counters, block, variant, nullptr, st),
                     "render_fused_noalloc");
 }
 

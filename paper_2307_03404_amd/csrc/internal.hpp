@@ -25,7 +25,15 @@ struct KSplit {
     int32_t* nb;
     int32_t* minfo;
     int64_t n_pad;
+    unsigned long long* gfix;   // deterministic scatter: fixed-point grid gradient, or nullptr
 };
+
+// Bytes of the fixed-point gradient buffer of the deterministic scatter
+// (FIX_SHIFT in kcommon.hpp), rounded up to 256.
+inline size_t fix_bytes(int64_t n_alloc, int record_floats) {
+    const size_t b = (size_t)n_alloc * (size_t)record_floats * sizeof(unsigned long long);
+    return (b + 255) & ~size_t(255);
+}
 
 inline int64_t split_pad(int64_t n_rays) { return (n_rays + 63) / 64 * 64; }
 inline size_t fused_workspace_bytes(int64_t n_rays) {
@@ -33,6 +41,7 @@ inline size_t fused_workspace_bytes(int64_t n_rays) {
 }
 inline KSplit split_state(void* ws, int64_t n_rays) {
     KSplit k;
+    k.gfix = nullptr;
     k.n_pad = split_pad(n_rays);
     char* p = static_cast<char*>(ws) + FUSED_WS_BYTES;
     k.sums = reinterpret_cast<double*>(p);
@@ -55,10 +64,13 @@ hipError_t launch_backward(const KGrid& g, const KRays& rs, const KOpts& op, con
                            const float* g_depth, float* grad_data, double* grad_pose,
                            hipStream_t st);
 
+// gfix: the zeroed fixed-point buffer of the deterministic scatter ([n_alloc][S] int64,
+// left zeroed), or nullptr for float atomics.
 hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,
                         const float* tgt_depth, const float* frame_weight, int want, float* rgb,
                         float* depth, double* loss, float* grad_data, double* grad_pose,
-                        int64_t* stats, unsigned* ws, int block, int variant, hipStream_t st);
+                        int64_t* stats, unsigned* ws, int block, int variant,
+                        unsigned long long* gfix, hipStream_t st);
 
 hipError_t launch_tv(const KGrid& g, float lambda_density, float lambda_sh, float eps,
                      float* grad_data, hipStream_t st);

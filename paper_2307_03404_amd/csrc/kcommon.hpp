@@ -41,6 +41,15 @@ struct RecL {
 enum { ACT_RELU_SHIFT = 0, ACT_SIGMOID = 1, ACT_IDENTITY = 2 };
 enum { LOSS_L1 = 0, LOSS_L2 = 1 };
 
+// Deterministic grid scatter: every merged contribution is rounded to a
+// fixed-point integer in units of 2^-FIX_SHIFT and added with 64-bit integer
+// atomics, which commute exactly, so the sum does not depend on the order in
+// which waves arrive; a last pass adds each integer sum, converted once, into
+// the float gradient.  Range +-2^(63 - FIX_SHIFT) = +-32768 per entry,
+// resolution 2^-48 = 3.6e-15.
+constexpr int FIX_SHIFT = 48;
+constexpr double FIX_SCALE = (double)(1ull << FIX_SHIFT);
+
 // Floats per record of SH degree deg (RecL<deg>::S at run time).
 __host__ __device__ __forceinline__ int record_floats(int deg) {
     return deg == 0 ? 4 : deg == 1 ? 16 : 28;

@@ -231,7 +231,7 @@ __device__ __forceinline__ int next_mark(const uint32_t* marks, int last, int o)
 // every lane must call this (lanes without a ray pass n = 0); steps where no
 // lane has an occupied cell are jumped over together.  Without GRID every
 // lane marches on its own.
-template <bool GRID, bool POSE, bool VIEW, int DEG>
+template <bool GRID, bool POSE, bool VIEW, int DEG, bool FIX = false>
 __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, const Ray& ray,
                                              const float Y[9], int n, const double Chat[3],
                                              double Dhat, const float gC[3], float gDr,
@@ -260,7 +260,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             if (work && sample_at(g, ray, k, s))
                 have = backward_sample<POSE, VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
                                                    pa, idx, w, gsig, gs);
-            scatter_merged<DEG>(have, s.base, idx, w, gsig, gs, Y, wc, grad);
+            scatter_merged<DEG, FIX>(have, s.base, idx, w, gsig, gs, Y, wc, grad);
             if (work) off = next_mark(marks, mark_last, off + 1);
         }
     } else if (GRID) {
@@ -300,7 +300,7 @@ __device__ __forceinline__ void ray_backward(const KGrid& g, const KOpts& op, co
             if (work)
                 have = backward_sample<POSE, VIEW, DEG>(g, op, ray, Y, GY, s, Chat, Dhat, gC, gDr, st,
                                                    pa, idx, w, gsig, gs);
-            scatter_merged<DEG>(have, s.base, idx, w, gsig, gs, Y, wc, grad);
+            scatter_merged<DEG, FIX>(have, s.base, idx, w, gsig, gs, Y, wc, grad);
             ++k;
         }
     } else if (marks && !mark_overflow) {
@@ -513,7 +513,7 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
                                                   float* __restrict__ grad,
                                                   double* __restrict__ grad_pose) {
     extern __shared__ float smem[];
-    WaveStage wc{nullptr, nullptr};
+    WaveStage wc{nullptr, nullptr, nullptr, nullptr};
     if (GRID) wc = wave_stage(smem);
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = r < rs.n;
@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(256) k_backward(KGrid g, KRays rs, KOpts op,
 // PH 2: backward).  The forward launch needs no LDS and few registers, so it
 // runs at the occupancy of a forward-only kernel; it leaves each ray's work
 // mask and backward inputs in `sp`, from which the backward launch resumes.
-template <bool GRID, bool POSE, bool VIEW, int PH, int DEG>
+template <bool GRID, bool POSE, bool VIEW, int PH, int DEG, bool FIX>
 __global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays rs, KOpts op,
                                                const float* __restrict__ tgt_rgb,
                                                const float* __restrict__ tgt_depth,
@@ -572,8 +572,11 @@ __global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays
                                                KSplit sp) {
     __shared__ int64_t s_tile;
     extern __shared__ float smem[];
-    WaveStage wc{nullptr, nullptr};
-    if (GRID && PH != 1) wc = wave_stage(smem);
+    WaveStage wc{nullptr, nullptr, nullptr, nullptr};
+    if (GRID && PH != 1) {
+        wc = wave_stage(smem);
+        wc.gfix = sp.gfix;
+    }
     const int64_t n_tiles = (rs.n + blockDim.x - 1) / blockDim.x;
     // Persistent form: workgroups take tiles in order from one queue counter
     // (ws[0]), so the tiles in flight at any time are neighbours in the
@@ -682,7 +685,7 @@ __global__ void __launch_bounds__(256, (PH == 1 ? 4 : 1)) k_fused(KGrid g, KRays
             fr.Cd[0] = fr.Cd[1] = fr.Cd[2] = fr.Dd = 0.0;
         }
         if ((GRID || POSE) && PH != 1)
-            ray_backward<GRID, POSE, VIEW, DEG>(g, op, ray, Y, nb, fr.Cd, fr.Dd, gC, gDr, grad, wc, pa, marks,
+            ray_backward<GRID, POSE, VIEW, DEG, FIX>(g, op, ray, Y, nb, fr.Cd, fr.Dd, gC, gDr, grad, wc, pa, marks,
                                            fr.mark_last, fr.mark_overflow);
         if (loss && PH != 2) {
             double lv[1] = {lval};
@@ -773,6 +776,20 @@ __global__ void __launch_bounds__(256) k_gn(KGrid g, KRays rs, KOpts op,
     seg_sum_atomic<GN_VALUES>(f, valid, vals, gn);
 }
 
+// Deterministic scatter, last step: grad += fixed-point sum x 2^-FIX_SHIFT
+// (one conversion of an exact integer sum), and the buffer is zeroed for the
+// next call.  Padding fields of a record are left alone.
+__global__ void __launch_bounds__(256) k_fix_finalize(unsigned long long* __restrict__ gfix,
+                                                      float* __restrict__ grad, int64_t n, int S,
+                                                      int used) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const long long v = (long long)gfix[i];
+        if (v != 0 && (int)(i % S) < used) grad[i] += (float)((double)v / FIX_SCALE);
+        gfix[i] = 0ull;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -844,13 +861,13 @@ static int device_cus() {
 // kernel's register and LDS use), never more than there are tiles.
 // The per-CU figure is cached per kernel and block size; concurrent callers
 // may both compute it, and they store the same value.
-template <bool GRID, bool POSE, bool VIEW, int PH, int DEG>
+template <bool GRID, bool POSE, bool VIEW, int PH, int DEG, bool FIX>
 static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
     static std::atomic<int> per_cu[4];                    // by block 64/128/256/512, 0 = unknown
     const int slot = block == 64 ? 0 : block == 128 ? 1 : block == 256 ? 2 : 3;
     int n = per_cu[slot].load(std::memory_order_relaxed);
     if (n <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW, PH, DEG>, block,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<GRID, POSE, VIEW, PH, DEG, FIX>, block,
                                                          lds) != hipSuccess || n <= 0)
             n = 1;
         per_cu[slot].store(n, std::memory_order_relaxed);
@@ -860,7 +877,7 @@ static unsigned resident_blocks(int block, size_t lds, int64_t tiles) {
     return (unsigned)(tiles < cap ? tiles : cap);
 }
 
-template <bool GRID, bool POSE, bool VIEW, int PH, int DEG>
+template <bool GRID, bool POSE, bool VIEW, int PH, int DEG, bool FIX>
 static void fused_phase(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
                         const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                         const float* fw, float* rgb, float* depth, double* loss, float* grad,
@@ -868,36 +885,41 @@ static void fused_phase(int64_t tiles, dim3 block, hipStream_t st, const KGrid& 
     const size_t lds = PH == 1 ? 0
                      : GRID ? (block.x / WAVE) * WAVE_LDS_FLOATS * sizeof(float)
                      : POSE ? (block.x / WAVE) * MARK_WORDS * WAVE * sizeof(uint32_t) : 0;
-    const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW, PH, DEG>(block.x, lds, tiles)
+    const dim3 grid(persistent ? resident_blocks<GRID, POSE, VIEW, PH, DEG, FIX>(block.x, lds, tiles)
                                : (unsigned)tiles);
-    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW, PH, DEG>), grid, block, lds, st, g, rs, op, tgt_rgb,
+    hipLaunchKernelGGL((k_fused<GRID, POSE, VIEW, PH, DEG, FIX>), grid, block, lds, st, g, rs, op, tgt_rgb,
                        tgt_depth, fw, rgb, depth, loss, grad, gp, stats, ws, persistent, sp);
 }
 
 // variant 0: one workgroup per tile; 1: persistent workgroups on the tile
 // queue; 2: a forward launch then a backward launch, both persistent, with
 // the per-ray state in the workspace
-template <bool GRID, bool POSE, bool VIEW, int DEG>
+template <bool GRID, bool POSE, bool VIEW, int DEG, bool FIX>
 static void fused_go(int64_t tiles, dim3 block, hipStream_t st, const KGrid& g, const KRays& rs,
                      const KOpts& op, const float* tgt_rgb, const float* tgt_depth,
                      const float* fw, float* rgb, float* depth, double* loss, float* grad,
-                     double* gp, int64_t* stats, unsigned* ws, int variant) {
+                     double* gp, int64_t* stats, unsigned* ws, int variant,
+                     unsigned long long* gfix) {
     if (variant == 2) {
-        const KSplit sp = split_state(ws, rs.n);
-        fused_phase<GRID, POSE, VIEW, 1, DEG>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb,
-                                              depth, loss, grad, gp, stats, ws, 1, sp);
-        fused_phase<GRID, POSE, VIEW, 2, DEG>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb,
-                                              depth, loss, grad, gp, stats, ws, 1, sp);
+        KSplit sp = split_state(ws, rs.n);
+        sp.gfix = gfix;
+        fused_phase<GRID, POSE, VIEW, 1, DEG, false>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw,
+                                                     rgb, depth, loss, grad, gp, stats, ws, 1, sp);
+        fused_phase<GRID, POSE, VIEW, 2, DEG, FIX>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw,
+                                                   rgb, depth, loss, grad, gp, stats, ws, 1, sp);
     } else {
-        fused_phase<GRID, POSE, VIEW, 0, DEG>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw, rgb,
-                                              depth, loss, grad, gp, stats, ws, variant, KSplit{});
+        KSplit sp{};
+        sp.gfix = gfix;
+        fused_phase<GRID, POSE, VIEW, 0, DEG, FIX>(tiles, block, st, g, rs, op, tgt_rgb, tgt_depth, fw,
+                                                   rgb, depth, loss, grad, gp, stats, ws, variant, sp);
     }
 }
 
 hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const float* tgt_rgb,
                         const float* tgt_depth, const float* frame_weight, int want, float* rgb,
                         float* depth, double* loss, float* grad_data, double* grad_pose,
-                        int64_t* stats, unsigned* ws, int block, int variant, hipStream_t st) {
+                        int64_t* stats, unsigned* ws, int block, int variant,
+                        unsigned long long* gfix, hipStream_t st) {
     if (want & 1) {
         // the grid scatter needs WAVE_LDS_FLOATS of LDS per wave: shrink the
         // workgroup if the device cannot give this many waves' worth
@@ -913,17 +935,31 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
     by_degree(g.deg, [&](auto D) {
         constexpr int DEG = decltype(D)::value;
         if (G && P) {
-            if (V) fused_go<true, true, true, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-            else fused_go<true, true, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+            if (V) {
+                if (gfix) fused_go<true, true, true, DEG, true>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, gfix);
+                else fused_go<true, true, true, DEG, false>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, gfix);
+            } else {
+                if (gfix) fused_go<true, true, false, DEG, true>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, gfix);
+                else fused_go<true, true, false, DEG, false>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, gfix);
+            }
         } else if (G) {
-            fused_go<true, false, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+            if (gfix) fused_go<true, false, false, DEG, true>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, gfix);
+            else fused_go<true, false, false, DEG, false>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, gfix);
         } else if (P) {
-            if (V) fused_go<false, true, true, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
-            else fused_go<false, true, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+            if (V) fused_go<false, true, true, DEG, false>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, nullptr);
+            else fused_go<false, true, false, DEG, false>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, nullptr);
         } else {
-            fused_go<false, false, false, DEG>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant);
+            fused_go<false, false, false, DEG, false>(tiles, blk, st, g, rs, op, tgt_rgb, tgt_depth, frame_weight, rgb, depth, loss, grad_data, grad_pose, sp, ws, variant, nullptr);
         }
     });
+    if (G && gfix) {
+        // fold the exact integer sums into the float gradient, once per entry
+        const int S = record_floats(g.deg);
+        const int64_t n = g.n_alloc * S;
+        const int64_t wgs = (n + 255) / 256;
+        hipLaunchKernelGGL(k_fix_finalize, dim3((unsigned)(wgs < (1 << 20) ? wgs : (1 << 20))), dim3(256), 0,
+                           st, gfix, grad_data, n, S, 1 + 3 * (g.deg + 1) * (g.deg + 1));
+    }
     return hipGetLastError();
 }
 

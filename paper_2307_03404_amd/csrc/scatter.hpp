@@ -38,6 +38,7 @@ struct WaveStage {
     float* sb;          // staged G operand
     float* sw;          // [WAVE][8] each lane's trilinear weights (16-byte aligned)
     uint32_t* marks;    // [MARK_WORDS][WAVE] each lane's work-position mask (fused kernel)
+    unsigned long long* gfix;   // deterministic mode: fixed-point gradient, else nullptr
 };
 
 // Must be reached by every lane of the wave, before its first scatter.  The
@@ -56,7 +57,7 @@ __device__ __forceinline__ WaveStage wave_stage(float* smem) {
         const int h = i >> 7, row = REC + ((i >> 5) & 3), c = i & 31;
         sb[((h << 5) + row) * STAGE_LD + c] = 0.f;
     }
-    return WaveStage{sb, sw, reinterpret_cast<uint32_t*>(sw + WAVE * 8)};
+    return WaveStage{sb, sw, reinterpret_cast<uint32_t*>(sw + WAVE * 8), nullptr};
 }
 
 // Staging addresses.  Operand element for MFMA step c (lanes 2c and 2c+1) and
@@ -82,7 +83,7 @@ constexpr int SMALL_PASS_LANES = 16;
 // idx[], trilinear weights w[]) in records of SH degree DEG (fields beyond
 // the record's used ones are staged as zeros and never written).  Must be
 // reached by every lane of the wave.
-template <int DEG>
+template <int DEG, bool FIX = false>
 __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int idx[8],
                                                const float w[8], float gsig, const float gs[3],
                                                const float Y[9], const WaveStage& wc,
@@ -180,7 +181,13 @@ __device__ __forceinline__ void scatter_merged(bool have, int64_t key, const int
             const int id0 = __builtin_amdgcn_readlane(idx[r & 3], ld);
             const int id1 = __builtin_amdgcn_readlane(idx[4 + (r & 3)], ld);
             const int vid = h ? id1 : id0;
-            if (vid >= 0 && j < USED) unsafeAtomicAdd(grad + (int64_t)vid * S + j, acc[r]);
+            if (vid >= 0 && j < USED) {
+                if (FIX)              // the deterministic (fixed-point) mode
+                    atomicAdd(wc.gfix + (int64_t)vid * S + j,
+                              (unsigned long long)__double2ll_rn((double)acc[r] * FIX_SCALE));
+                else
+                    unsafeAtomicAdd(grad + (int64_t)vid * S + j, acc[r]);
+            }
         }
     }
 }

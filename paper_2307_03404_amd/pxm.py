@@ -16,7 +16,9 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpxm.so")
+# PXM_LIBRARY selects another build of the same library (e.g. one whose host
+# code is built with sanitizers, for the CPU-side argument-check tests)
+LIB_PATH = os.environ.get("PXM_LIBRARY") or os.path.join(_PKG, "libpxm.so")
 REC = 28                      # floats per record at SH degree 2
 
 
@@ -27,7 +29,7 @@ def record_floats(sh_degree: int) -> int:
 COLOR_RELU_SHIFT, COLOR_SIGMOID, COLOR_IDENTITY = 0, 1, 2
 DEPTH_L1, DEPTH_L2 = 0, 1
 FLAG_POSE_VIEWDIR = 1
-WANT_GRID, WANT_POSE, WANT_STATS = 1, 2, 4
+WANT_GRID, WANT_POSE, WANT_STATS, WANT_DETERMINISTIC = 1, 2, 4, 8
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "device error",
           4: "workspace too small"}

@@ -128,7 +128,7 @@ def test_backward_and_fused_argument_checks():
     assert L.pxm_render_backward_grid(*args, FAKE, FAKE, FAKE, FAKE, FAKE, None, None) == 1
     assert L.pxm_render_backward_pose(*args, FAKE, FAKE, FAKE, None, FAKE, FAKE, None) == 1
     # fused: unknown want bit, missing grad buffers, small workspace
-    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 8, None, None, None, None, None, None,
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 16, None, None, None, None, None, None,
                               FAKE, 4096, None) == 1
     assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 1, None, None, None, None, None, None,
                               FAKE, 4096, None) == 1
@@ -240,7 +240,7 @@ def test_noalloc_fused_argument_checks_and_size_limit():
     L = pxm.lib()
     g, r, o = good_grid(), good_rays(), good_opts()
     args = [C.byref(g), C.byref(r), C.byref(o)]
-    assert L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 8, None, None, None, None, None,
+    assert L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 16, None, None, None, None, None,
                                       None, None) == 1
     assert L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 1, None, None, None, None, None,
                                       None, None) == 1
@@ -265,3 +265,25 @@ def test_noalloc_fused_argument_checks_and_size_limit():
     text = open(HEADER).read()
     assert f"#define PXM_NOALLOC_MAX_SPLIT_RAYS {pxm.NOALLOC_MAX_SPLIT_RAYS}" in text
     assert pxm.NOALLOC_SCRATCH_BYTES == 32 << 20 and "(32u << 20)" in text
+
+
+def test_deterministic_scatter_workspace_and_noalloc_refusal():
+    """The deterministic grid scatter adds an n_alloc x S int64 buffer to the
+    fused workspace, and the allocation-free entry point refuses it."""
+    L = pxm.lib()
+    g, r, o = good_grid(), good_rays(), good_opts()
+    args = [C.byref(g), C.byref(r), C.byref(o)]
+    base = 256 + 64 * 184
+    assert L.pxm_workspace_bytes(*args, 3) == base
+    assert L.pxm_workspace_bytes(*args, 3 | 8) == base + 256 * ((10 * 28 * 8 + 255) // 256)
+    assert L.pxm_workspace_bytes(*args, 2 | 8) == base          # no grid gradient, no buffer
+    g.sh_degree = 1
+    assert L.pxm_workspace_bytes(*args, 1 | 8) == base + 256 * ((10 * 16 * 8 + 255) // 256)
+    g.sh_degree = 2
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 1 | 8, None, None, None, FAKE, None, None,
+                              FAKE, base, None) == 4                # workspace too small
+    assert L.pxm_render_fused(*args, FAKE, FAKE, FAKE, 16, None, None, None, FAKE, None, None,
+                              FAKE, 1 << 20, None) == 1             # unknown bit
+    st = L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 1 | 8, None, None, None, FAKE, None,
+                                    None, None)
+    assert st == 2 and b"workspace" in L.pxm_last_error()
