@@ -397,11 +397,12 @@ def test_tv_c2(c2):
     assert_r28(np_(grad)[:, 1:], ref[:, 1:], TAU_GRAD, "tv sh")
 
 
-def test_tv_dense_c1(c1):
+@pytest.mark.parametrize("occupancy", [True, False])
+def test_tv_dense_c1(c1, occupancy):
     pxm = _dev()
     wl, _ = c1
     _, ref = oracle.tv(wl.grid, 0.3, 0.05, 1e-4)
-    g = pxm.grid_to_device(wl.grid)
+    g = pxm.grid_to_device(wl.grid, occupancy=occupancy)
     base = torch.full_like(g.data, 0.25)
     grad = pxm.tv_grad(g, 0.3, 0.05, 1e-4, grad_data=base)     # accumulates
     torch.cuda.synchronize()
