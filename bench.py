@@ -153,6 +153,34 @@ def copy_calibration(nbytes=1 << 30, reps=3):
           flush=True)
 
 
+def cache_probe():
+    """Streaming-read bandwidth of buffers from L2-resident to HBM-resident
+    sizes (pxm_probe_read_bandwidth: each XCD reads its own eighth), the
+    cache-level ceilings beside which the fused kernel's traffic is read."""
+    import torch
+    from paper_2307_03404_amd import pxm
+    out = []
+    sink = torch.empty(2048 * 256, dtype=torch.float32, device="cuda")
+    for mib in (4, 16, 32, 64, 128, 224, 1024, 4096):
+        nbytes = mib << 20
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        passes = max(1, int((16 << 30) // nbytes))
+        pxm.probe_read_bandwidth(buf, 1, sink)                # warm-up: caches filled
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pxm.probe_read_bandwidth(buf, passes, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out.append({"buffer_mib": mib, "passes": passes, "ms": ms,
+                    "read_gbs": nbytes * passes / (ms * 1e-3) / 1e9})
+        log(f"read probe {mib} MiB x {passes}: {out[-1]['read_gbs']:.0f} GB/s")
+        del buf
+    return {"metric": "streaming read bandwidth by buffer size (each XCD reads its own eighth)",
+            "unit": "GB/s", "n_gpus": 1, "data": "synthetic", "probe": out}
+
+
 def cpu_model():
     """Host CPU model name (from /proc/cpuinfo), or the platform string."""
     try:
@@ -452,6 +480,8 @@ def main():
                     help="time the dynamic-grid edits (prune, grow 256^3 -> 511^3) instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (for scaling HBM byte counters)")
+    ap.add_argument("--cache-probe", action="store_true",
+                    help="only measure streaming-read bandwidth from L2- to HBM-resident sizes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: there is no multi-GPU path; run with --gpus 1",
@@ -465,6 +495,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cache_probe:
+        print(json.dumps(cache_probe()), flush=True)
         return
     if args.grid_edit:
         print(json.dumps(grid_edit_bench(args)), flush=True)

@@ -373,6 +373,18 @@ int pxm_render_fused_noalloc(const pxm_grid *grid, const pxm_rays *rays, const p
                              double *loss, float *grad_data, double *grad_pose, int64_t *stats,
                              void *stream);
 
+/*
+ * Measurement aid (not part of the method): streaming-read bandwidth of
+ * `bytes` (a multiple of 128) of device memory at `buf` (16-byte aligned),
+ * read `passes` times by 2048 workgroups of 256 lanes with float4 loads,
+ * workgroup b reading only the (b % 8)-th eighth of the buffer (the XCD
+ * workgroup b runs on), so the per-XCD working set is bytes / 8: ~32 MB in
+ * total stays in the L2s, ~256 MB in the Infinity Cache.  Time it with events
+ * on `stream`.  sink: >= 2048 * 256 floats of device memory, overwritten.
+ */
+int pxm_probe_read_bandwidth(const void *buf, size_t bytes, int32_t passes, float *sink,
+                             size_t sink_floats, void *stream);
+
 /* Workspace bytes pxm_render_fused needs for these arguments and `want`, under
  * any launch tuning: 256 + 184 * (n_rays rounded up to 64), plus, with
  * PXM_WANT_GRID | PXM_WANT_DETERMINISTIC, 8 * n_alloc * S rounded up to 256. */

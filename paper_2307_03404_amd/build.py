@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpxm.so")
-SOURCES = ["render.hip", "tv.hip", "adam.hip", "optim.hip", "occ.hip", "edit.hip", "abi.hip"]
+SOURCES = ["render.hip", "tv.hip", "adam.hip", "optim.hip", "occ.hip", "edit.hip", "probe.hip", "abi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -418,6 +418,19 @@ int pxm_grid_prune(const pxm_grid* grid, float tau, int32_t* link_out, float* da
                     "grid_prune");
 }
 
+int pxm_probe_read_bandwidth(const void* buf, size_t bytes, int32_t passes, float* sink,
+                             size_t sink_floats, void* stream) {
+    if (!buf || !sink) return fail(PXM_INVALID_ARGUMENT, "buf / sink is NULL");
+    if (reinterpret_cast<uintptr_t>(buf) & 15) return fail(PXM_INVALID_ARGUMENT, "buf must be 16-byte aligned");
+    if (bytes < 128 || (bytes % 128) != 0) return fail(PXM_INVALID_ARGUMENT, "bytes must be a positive multiple of 128");
+    if (passes < 1) return fail(PXM_INVALID_ARGUMENT, "passes < 1");
+    const int n_wg = 2048;                                  // a multiple of the 8 XCDs
+    if (sink_floats < (size_t)n_wg * 256)
+        return fail(PXM_WORKSPACE_TOO_SMALL, "sink needs %d floats", n_wg * 256);
+    return launched(pxm::launch_probe_read(static_cast<const float4*>(buf), (int64_t)(bytes / 16), passes, sink,
+                                           n_wg, (hipStream_t)stream), "probe_read_bandwidth");
+}
+
 // ---------------------------------------------------------------------------
 // Allocation-free fused step: the workspace is a file-scope device array.
 // ---------------------------------------------------------------------------

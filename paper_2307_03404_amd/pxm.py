@@ -64,6 +64,7 @@ EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backwar
            "pxm_tv_grad", "pxm_render_fused", "pxm_render_fused_noalloc", "pxm_pose_adam",
            "pxm_grid_rmsprop", "pxm_render_gn", "pxm_pose_gn",
            "pxm_grid_edit_workspace_bytes", "pxm_grid_upsample_link", "pxm_grid_upsample_data",
+           "pxm_probe_read_bandwidth",
            "pxm_grid_prune",
            "pxm_workspace_bytes",
            "pxm_occupancy_words", "pxm_build_occupancy",
@@ -95,6 +96,8 @@ def lib():
         L.pxm_grid_rmsprop.argtypes = [i64, i32, P, P, P, f32, f32, f32, f32, P]
         L.pxm_render_gn.argtypes = [G, R, O, P, P, P, P, P]
         L.pxm_pose_gn.argtypes = [i32, P, P, f32, P]
+        L.pxm_probe_read_bandwidth.argtypes = [P, sz, i32, P, sz, P]
+        L.pxm_probe_read_bandwidth.restype = C.c_int
         L.pxm_grid_edit_workspace_bytes.argtypes = [G]
         L.pxm_grid_edit_workspace_bytes.restype = sz
         L.pxm_grid_upsample_link.argtypes = [G, P, P, P, sz, P]
@@ -520,6 +523,17 @@ def grid_prune(grid: DeviceGrid, tau: float, ws=None, in_place=False, occupancy=
     if occupancy:
         out.build_occupancy(stream)
     return out
+
+
+def probe_read_bandwidth(buf: torch.Tensor, passes: int, sink: torch.Tensor = None, stream=None):
+    """Streaming reads of `buf` (each XCD its own eighth), `passes` times:
+    a cache-level read ceiling to compare the fused kernel's traffic with."""
+    if sink is None:
+        sink = torch.empty(2048 * 256, dtype=torch.float32, device=buf.device)
+    nbytes = buf.numel() * buf.element_size()
+    _check("probe_read_bandwidth", lib().pxm_probe_read_bandwidth(
+        _ptr(buf), nbytes, int(passes), _ptr(sink), sink.numel(), _stream(stream)))
+    return sink
 
 
 def set_tuning(block: int, variant: int):

@@ -287,3 +287,13 @@ def test_deterministic_scatter_workspace_and_noalloc_refusal():
     st = L.pxm_render_fused_noalloc(*args, FAKE, FAKE, FAKE, 1 | 8, None, None, None, FAKE, None,
                                     None, None)
     assert st == 2 and b"workspace" in L.pxm_last_error()
+
+
+def test_read_probe_argument_checks():
+    L = pxm.lib()
+    assert L.pxm_probe_read_bandwidth(None, 1 << 20, 1, FAKE, 2048 * 256, None) == 1
+    assert L.pxm_probe_read_bandwidth(FAKE, 1 << 20, 1, None, 2048 * 256, None) == 1
+    assert L.pxm_probe_read_bandwidth(FAKE + 4, 1 << 20, 1, FAKE, 2048 * 256, None) == 1
+    assert L.pxm_probe_read_bandwidth(FAKE, 100, 1, FAKE, 2048 * 256, None) == 1
+    assert L.pxm_probe_read_bandwidth(FAKE, 1 << 20, 0, FAKE, 2048 * 256, None) == 1
+    assert L.pxm_probe_read_bandwidth(FAKE, 1 << 20, 1, FAKE, 1000, None) == 4
