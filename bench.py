@@ -35,7 +35,10 @@ TRAFFIC_PROFILES = {
     "c4_room512_8x1200x680_mapping": "k_fused_c4_room512_8x816k_rays_traffic.md",
     "c5_room512_64frames_mixed": "k_fused_c5_room512_64_mixed_frames_traffic.md",
 }
-KERNEL_SOURCES = ("include/pxm.h", "paper_2307_03404_amd/csrc")
+# the translation unit of the fused kernel: its HBM counters stay valid while
+# these files are unchanged
+KERNEL_SOURCES = ("paper_2307_03404_amd/csrc/render.hip", "paper_2307_03404_amd/csrc/scatter.hpp",
+                  "paper_2307_03404_amd/csrc/kcommon.hpp", "paper_2307_03404_amd/csrc/internal.hpp")
 
 
 def log(*a):

@@ -418,6 +418,17 @@ int pxm_grid_prune(const pxm_grid* grid, float tau, int32_t* link_out, float* da
                     "grid_prune");
 }
 
+}  // extern "C"
+
+namespace pxm {
+// probe.hip: n_wg workgroups of 256 (a multiple of 8), `passes` reads of the
+// n4 float4s, XCD x reading its own eighth
+hipError_t launch_probe_read(const float4* buf, int64_t n4, int passes, float* sink, int n_wg,
+                             hipStream_t st);
+}  // namespace pxm
+
+extern "C" {
+
 int pxm_probe_read_bandwidth(const void* buf, size_t bytes, int32_t passes, float* sink,
                              size_t sink_floats, void* stream) {
     if (!buf || !sink) return fail(PXM_INVALID_ARGUMENT, "buf / sink is NULL");

@@ -106,9 +106,4 @@ hipError_t launch_upsample_data(const KGrid& g, const int32_t* link_fine, int64_
 hipError_t launch_prune(const KGrid& g, float tau, int32_t* link_out, float* data_out, int64_t* n_out, void* ws,
                         hipStream_t st);
 
-// Read-bandwidth probe (probe.hip): n_wg workgroups of 256 (a multiple of 8),
-// `passes` reads of the n4 float4s, XCD x reading its own eighth.
-hipError_t launch_probe_read(const float4* buf, int64_t n4, int passes, float* sink, int n_wg,
-                             hipStream_t st);
-
 }  // namespace pxm

@@ -4,7 +4,8 @@
 // XCDs), so giving XCD x its own eighth of the buffer keeps each L2's working
 // set at bytes / 8: a buffer of up to ~32 MB stays in the eight 4 MB L2s, up
 // to ~256 MB in the Infinity Cache, larger ones stream from HBM.
-#include "internal.hpp"
+#include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace pxm {
 

@@ -2,6 +2,7 @@
 byte model and the rule that HBM counters are reported only for the kernel
 sources, workload and launch shape they were taken on."""
 import os
+import re
 import subprocess
 import sys
 
@@ -64,7 +65,19 @@ def test_roofline_fraction_is_measured_traffic_over_peak():
 
 
 def test_sources_digest_covers_the_kernel_sources():
-    files = bench.KERNEL_SOURCES
-    assert "include/pxm.h" in files and "paper_2307_03404_amd/csrc" in files
+    # the fused kernel's translation unit: render.hip and every header it includes
+    files = set(bench.KERNEL_SOURCES)
+    csrc = os.path.join(ROOT, "paper_2307_03404_amd", "csrc")
+    pending = ["render.hip"]
+    seen = set()
+    while pending:
+        f = pending.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        with open(os.path.join(csrc, f)) as fh:
+            src = fh.read()
+        pending += re.findall(r'^#include "([^"]+)"', src, re.M)
+    assert {"paper_2307_03404_amd/csrc/" + f for f in seen} == files
     d = bench.sources_sha256()
     assert len(d) == 64 and d == bench.sources_sha256()
