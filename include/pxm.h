@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define PXM_ABI_VERSION 6   /* 6: SH degree 0/1 records (pxm_grid.sh_degree) */
+#define PXM_ABI_VERSION 7   /* 7: pxm_tv_grad_set; 6: SH degree 0/1 records (pxm_grid.sh_degree) */
 #define PXM_RECORD 28          /* floats per vertex at SH degree 2: density + 3 x 9 SH */
 #define PXM_RECORD_FLOATS(d) ((d) == 0 ? 4 : (d) == 1 ? 16 : 28)   /* per SH degree */
 
@@ -180,6 +180,18 @@ int pxm_render_backward_pose(const pxm_grid *grid, const pxm_rays *rays, const p
  */
 int pxm_tv_grad(const pxm_grid *grid, float lambda_density, float lambda_sh, float eps,
                 float *grad_data, void *stream);
+
+/*
+ * The same TV gradient written instead of added: for every allocated vertex
+ * the link table reaches, grad_data[v][m] = dTV/d val_m(v) for its used
+ * fields m < 1 + 3 (d+1)^2; the padding fields of a record, and records no
+ * link reaches, are left as they are.  Arguments and errors as
+ * pxm_tv_grad.  It saves reading grad_data: a step that zeroes the gradient
+ * can call this first and then let pxm_render_fused add the rendering
+ * gradient onto it.
+ */
+int pxm_tv_grad_set(const pxm_grid *grid, float lambda_density, float lambda_sh, float eps,
+                    float *grad_data, void *stream);
 
 /*
  * Fused batched step: forward (Eq. 1-3), the loss of Eq. 4, 5 and 11, and the

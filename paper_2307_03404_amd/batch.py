@@ -308,10 +308,12 @@ class MappingLoop:
         if self.ws is None:
             self.ws = pxm.new_workspace(self.grid, rays, self.opts, pxm.WANT_GRID)
         self.loss.zero_()
+        # the gradient is zero here (grid_rmsprop clears it): the TV term is
+        # written first and the rendering backward adds onto it
+        if self.tv[0] or self.tv[1]:
+            pxm.tv_grad_set(self.grid, self.tv[0], self.tv[1], self.tv[2], self.grad)
         pxm.render_fused(self.grid, rays, self.opts, rgb, depth, w, pxm.WANT_GRID, loss=self.loss,
                          grad_data=self.grad, ws=self.ws)
-        if self.tv[0] or self.tv[1]:
-            pxm.tv_grad(self.grid, self.tv[0], self.tv[1], self.tv[2], self.grad)
         pxm.grid_rmsprop(self.grid.data, self.grad, self.state, self.lr[0], self.lr[1],
                          self.alpha, self.eps, sh_degree=self.grid.sh_degree)
         return self.loss.sum()

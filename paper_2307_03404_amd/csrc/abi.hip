@@ -213,8 +213,8 @@ int pxm_render_backward_pose(const pxm_grid* grid, const pxm_rays* rays, const p
                     "render_backward_pose");
 }
 
-int pxm_tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, float eps,
-                float* grad_data, void* stream) {
+static int tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, float eps,
+                   float* grad_data, bool set, void* stream) {
     PXM_TRY(check_grid(grid));
     if (!grad_data && grid->n_alloc > 0) return fail(PXM_INVALID_ARGUMENT, "grad_data is NULL");
     if (!finite(lambda_density) || !finite(lambda_sh))
@@ -223,8 +223,18 @@ int pxm_tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, flo
     if (grid->n_alloc == 0) return PXM_OK;                          // no vertex has a term
     if (reinterpret_cast<uintptr_t>(grad_data) & 15)
         return fail(PXM_INVALID_ARGUMENT, "grad_data must be 16-byte aligned");
-    return launched(pxm::launch_tv(kgrid(grid), lambda_density, lambda_sh, eps, grad_data,
-                                   (hipStream_t)stream), "tv_grad");
+    return launched(pxm::launch_tv(kgrid(grid), lambda_density, lambda_sh, eps, grad_data, set,
+                                   (hipStream_t)stream), set ? "tv_grad_set" : "tv_grad");
+}
+
+int pxm_tv_grad(const pxm_grid* grid, float lambda_density, float lambda_sh, float eps,
+                float* grad_data, void* stream) {
+    return tv_grad(grid, lambda_density, lambda_sh, eps, grad_data, false, stream);
+}
+
+int pxm_tv_grad_set(const pxm_grid* grid, float lambda_density, float lambda_sh, float eps,
+                    float* grad_data, void* stream) {
+    return tv_grad(grid, lambda_density, lambda_sh, eps, grad_data, true, stream);
 }
 
 size_t pxm_occupancy_words(const pxm_grid* grid) {

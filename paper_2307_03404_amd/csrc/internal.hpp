@@ -72,8 +72,9 @@ hipError_t launch_fused(const KGrid& g, const KRays& rs, const KOpts& op, const 
                         int64_t* stats, unsigned* ws, int block, int variant,
                         unsigned long long* gfix, hipStream_t st);
 
+// set: grad_data = dTV for the visited records' used fields, else += dTV
 hipError_t launch_tv(const KGrid& g, float lambda_density, float lambda_sh, float eps,
-                     float* grad_data, hipStream_t st);
+                     float* grad_data, bool set, hipStream_t st);
 
 // Occupancy bitfield: level-0 32-bit words (two per 4^3-cell block), 4^3
 // blocks per axis, 8^3 bricks per axis, level-1 words for a lattice of R

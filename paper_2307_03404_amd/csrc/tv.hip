@@ -24,7 +24,13 @@
 // same L2.  Each phase issues all of a thread's global loads before it uses
 // any (links, staged records, gradient entries), so a phase costs one memory
 // round trip: the gradient read-modify-writes, one per item in turn, were the
-// longest chain.
+// longest chain.  The allocated vertices of all eight sub-bricks are listed
+// first, so that the records of the next non-empty sub-brick are requested
+// before the current one is computed and arrive while it is.
+//
+// SET writes the gradient (grad = dTV) instead of adding to it, which saves
+// the read of the gradient: a step that zeroes its gradient can run the TV
+// term first and let the rendering backward add onto it.
 #include "internal.hpp"
 
 namespace pxm {
@@ -42,16 +48,17 @@ constexpr int TV_ITEMS = TB * TB * TB * 32 / TV_THREADS;   // vertex-field items
 __device__ __forceinline__ int hidx8(int x, int y, int z) { return (x * TH8 + y) * TH8 + z; }
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (x * TH + y) * TH + z; }
 
-template <int DEG>
+template <int DEG, bool SET>
 __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float lam_sh, float eps,
                                                    float* __restrict__ grad, int nby, int nbz) {
     constexpr int S = RecL<DEG>::S, Q = RecL<DEG>::Q, USED = RecL<DEG>::USED;
     constexpr int STAGE_ITERS = (TH3 * Q + TV_THREADS - 1) / TV_THREADS;   // staged float4 per thread
+    static_assert(TV_THREADS == 4 * WAVE, "one wave lists two sub-bricks");
     __shared__ int s_id8[TH83];             // links of the block halo (-1 empty or outside)
     __shared__ int s_id[TH3];               // links of the current sub-brick halo
     __shared__ float s_v[S][PLANE];         // field m of sub-halo position p at s_v[m][p]
-    __shared__ int s_list[TB * TB * TB];    // sub-halo positions of allocated sub-brick vertices
-    __shared__ int s_n;
+    __shared__ int s_list[8][TB * TB * TB]; // per sub-brick: sub-halo positions of its allocated vertices
+    __shared__ int s_n[8];
     const int t = threadIdx.x;
     const int64_t block = xcd_tile(blockIdx.x, gridDim.x);
     const int bz = (int)(block % nbz), by = (int)((block / nbz) % nby);
@@ -84,27 +91,28 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
         }
     }
     __syncthreads();
-#pragma unroll 1
-    for (int sb = 0; sb < 8; ++sb) {
-        // sub-brick origin in block-halo coordinates (its halo starts one lower)
+    // sub-brick sb: origin 4 * (bit 2, bit 1, bit 0 of sb) in block-halo
+    // coordinates (its halo starts one lower).  Wave w lists sub-bricks w
+    // and w + 4 (64 vertices each, one per lane).
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int sb = t / WAVE + 4 * j, l = t % WAVE;
         const int ox = 4 * ((sb >> 2) & 1), oy = 4 * ((sb >> 1) & 1), oz = 4 * (sb & 1);
-        // compact its allocated vertices (one wave covers the 64 of them)
-        if (t < TB * TB * TB) {
-            const int ix = t / (TB * TB) + 1, iy = (t / TB) % TB + 1, iz = t % TB + 1;
-            const bool a = s_id8[hidx8(ox + ix, oy + iy, oz + iz)] >= 0;
-            const unsigned long long m = __ballot(a);
-            if (a) s_list[__popcll(m & ((1ull << t) - 1))] = hidx(ix, iy, iz);
-            if (t == 0) s_n = __popcll(m);
-        }
-        __syncthreads();
-        const int n = s_n;
-        if (n == 0) {                                       // workgroup-uniform
-            __syncthreads();                                // s_n and s_list are rewritten next
-            continue;
-        }
-        // stage the sub-halo links and records: Q lanes per position, one
-        // float4 each; all of a thread's loads are issued before its LDS writes
-        float4 wv[STAGE_ITERS];
+        const int ix = l / (TB * TB) + 1, iy = (l / TB) % TB + 1, iz = l % TB + 1;
+        const bool a = s_id8[hidx8(ox + ix, oy + iy, oz + iz)] >= 0;
+        const unsigned long long m = __ballot(a);
+        if (a) s_list[sb][__popcll(m & ((1ull << l) - 1))] = hidx(ix, iy, iz);
+        if (l == 0) s_n[sb] = __popcll(m);
+    }
+    __syncthreads();
+    auto next_nonempty = [&](int sb) {
+        while (sb < 8 && s_n[sb] == 0) ++sb;                // workgroup-uniform
+        return sb;
+    };
+    // the sub-halo records of sub-brick sb: Q lanes per position, one float4 each
+    float4 wv[STAGE_ITERS];
+    auto request = [&](int sb) {
+        const int ox = 4 * ((sb >> 2) & 1), oy = 4 * ((sb >> 1) & 1), oz = 4 * (sb & 1);
 #pragma unroll
         for (int k = 0; k < STAGE_ITERS; ++k) {
             const int i = t + k * TV_THREADS;
@@ -113,15 +121,24 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
                 const int p = i / Q, q = i - Q * p;
                 const int hx = p / (TH * TH), hy = (p / TH) % TH, hz = p % TH;
                 const int id = s_id8[hidx8(ox + hx, oy + hy, oz + hz)];
-                if (q == 0) s_id[p] = id;
                 if (id >= 0) wv[k] = reinterpret_cast<const float4*>(g.data + (int64_t)id * S)[q];
             }
         }
+    };
+    int sb = next_nonempty(0);
+    if (sb < 8) request(sb);
+#pragma unroll 1
+    while (sb < 8) {
+        const int ox = 4 * ((sb >> 2) & 1), oy = 4 * ((sb >> 1) & 1), oz = 4 * (sb & 1);
 #pragma unroll
         for (int k = 0; k < STAGE_ITERS; ++k) {
             const int i = t + k * TV_THREADS;
             if (i < TH3 * Q) {
                 const int p = i / Q, q = i - Q * p;
+                if (q == 0) {
+                    const int hx = p / (TH * TH), hy = (p / TH) % TH, hz = p % TH;
+                    s_id[p] = s_id8[hidx8(ox + hx, oy + hy, oz + hz)];
+                }
                 s_v[4 * q][p] = wv[k].x;
                 s_v[4 * q + 1][p] = wv[k].y;
                 s_v[4 * q + 2][p] = wv[k].z;
@@ -129,33 +146,17 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             }
         }
         __syncthreads();
-        // 32 lanes per allocated vertex, lane m < USED takes field m.  A thread
-        // has at most TV_ITEMS items (n <= 64); their gradient entries are
-        // read first, so the read-modify-writes cost one round trip, not one each.
-        float gv[TV_ITEMS];
-        int64_t ga[TV_ITEMS];
-#pragma unroll
-        for (int k = 0; k < TV_ITEMS; ++k) {
-            const int it = t + k * TV_THREADS;
-            const int m = it & 31;
-            ga[k] = -1;
-            gv[k] = 0.f;
-            if (it < n * 32 && m < USED) {
-                ga[k] = (int64_t)s_id[s_list[it >> 5]] * S + m;
-                gv[k] = grad[ga[k]];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < TV_ITEMS; ++k) {
-            if (ga[k] < 0) continue;
-            const int it = t + k * TV_THREADS;
-            const int m = it & 31;
-            const int c = s_list[it >> 5];
+        const int nx = next_nonempty(sb + 1);
+        if (nx < 8) request(nx);                            // in flight while sb is computed
+        const int n = s_n[sb];
+        const int* list = s_list[sb];
+        // 32 lanes per allocated vertex, lane m < USED takes field m; a thread
+        // has at most TV_ITEMS items (n <= 64)
+        auto dtv = [&](int c, int m) -> float {
             const int ix = c / (TH * TH), iy = (c / TH) % TH, iz = c % TH;
             const int x = x0 + ox + ix - 1, y = y0 + oy + iy - 1, z = z0 + oz + iz - 1;
             const float* plane = s_v[m];
             auto val = [&](int p) -> float { return plane[p]; };
-            const float lam = m == 0 ? lam_d : lam_sh;
             const float v0 = val(c);
             float acc = 0.f;
             if (x < X - 1 && y < Y - 1 && z < Z - 1) {
@@ -185,26 +186,67 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
                 const float dz = v0 - c0;
                 acc += dz * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            grad[ga[k]] = gv[k] + lam * acc;
+            return (m == 0 ? lam_d : lam_sh) * acc;
+        };
+        if constexpr (SET) {
+#pragma unroll
+            for (int k = 0; k < TV_ITEMS; ++k) {
+                const int it = t + k * TV_THREADS;
+                const int m = it & 31;
+                if (it < n * 32 && m < USED) {
+                    const int c = list[it >> 5];
+                    grad[(int64_t)s_id[c] * S + m] = dtv(c, m);
+                }
+            }
+        } else {
+            // the items' gradient entries are read first, so the
+            // read-modify-writes cost one round trip, not one each
+            float gv[TV_ITEMS];
+            int64_t ga[TV_ITEMS];
+#pragma unroll
+            for (int k = 0; k < TV_ITEMS; ++k) {
+                const int it = t + k * TV_THREADS;
+                const int m = it & 31;
+                ga[k] = -1;
+                gv[k] = 0.f;
+                if (it < n * 32 && m < USED) {
+                    ga[k] = (int64_t)s_id[list[it >> 5]] * S + m;
+                    gv[k] = grad[ga[k]];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < TV_ITEMS; ++k) {
+                if (ga[k] < 0) continue;
+                const int it = t + k * TV_THREADS;
+                grad[ga[k]] = gv[k] + dtv(list[it >> 5], it & 31);
+            }
         }
         __syncthreads();                                    // LDS reused by the next sub-brick
+        sb = nx;
     }
 }
 
-hipError_t launch_tv(const KGrid& g, float lambda_density, float lambda_sh, float eps,
-                     float* grad_data, hipStream_t st) {
+template <bool SET>
+static void tv_go(const KGrid& g, float lambda_density, float lambda_sh, float eps, float* grad_data,
+                  hipStream_t st) {
     const int nbx = (g.R[0] + TB8 - 1) / TB8, nby = (g.R[1] + TB8 - 1) / TB8;
     const int nbz = (g.R[2] + TB8 - 1) / TB8;
     const int64_t nb = (int64_t)nbx * nby * nbz;
     if (g.deg == 0)
-        hipLaunchKernelGGL(k_tv<0>, dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
+        hipLaunchKernelGGL((k_tv<0, SET>), dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
                            lambda_sh, eps, grad_data, nby, nbz);
     else if (g.deg == 1)
-        hipLaunchKernelGGL(k_tv<1>, dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
+        hipLaunchKernelGGL((k_tv<1, SET>), dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
                            lambda_sh, eps, grad_data, nby, nbz);
     else
-        hipLaunchKernelGGL(k_tv<2>, dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
+        hipLaunchKernelGGL((k_tv<2, SET>), dim3((unsigned)nb), dim3(TV_THREADS), 0, st, g, lambda_density,
                            lambda_sh, eps, grad_data, nby, nbz);
+}
+
+hipError_t launch_tv(const KGrid& g, float lambda_density, float lambda_sh, float eps,
+                     float* grad_data, bool set, hipStream_t st) {
+    if (set) tv_go<true>(g, lambda_density, lambda_sh, eps, grad_data, st);
+    else tv_go<false>(g, lambda_density, lambda_sh, eps, grad_data, st);
     return hipGetLastError();
 }
 

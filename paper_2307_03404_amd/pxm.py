@@ -61,8 +61,8 @@ class _Opts(C.Structure):
 _lib = None
 _lock = threading.Lock()
 EXPORTS = ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
-           "pxm_tv_grad", "pxm_render_fused", "pxm_render_fused_noalloc", "pxm_pose_adam",
-           "pxm_grid_rmsprop", "pxm_render_gn", "pxm_pose_gn",
+           "pxm_tv_grad", "pxm_tv_grad_set", "pxm_render_fused", "pxm_render_fused_noalloc",
+           "pxm_pose_adam", "pxm_grid_rmsprop", "pxm_render_gn", "pxm_pose_gn",
            "pxm_grid_edit_workspace_bytes", "pxm_grid_upsample_link", "pxm_grid_upsample_data",
            "pxm_probe_read_bandwidth",
            "pxm_grid_prune",
@@ -90,6 +90,7 @@ def lib():
         L.pxm_render_backward_grid.argtypes = [G, R, O, P, P, P, P, P, P, P]
         L.pxm_render_backward_pose.argtypes = [G, R, O, P, P, P, P, P, P, P]
         L.pxm_tv_grad.argtypes = [G, f32, f32, f32, P, P]
+        L.pxm_tv_grad_set.argtypes = [G, f32, f32, f32, P, P]
         L.pxm_render_fused.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P, sz, P]
         L.pxm_render_fused_noalloc.argtypes = [G, R, O, P, P, P, i32, P, P, P, P, P, P, P]
         L.pxm_pose_adam.argtypes = [i32, P, P, P, f32, f32, f32, f32, P]
@@ -116,7 +117,7 @@ def lib():
         L.pxm_status_string.restype = C.c_char_p
         L.pxm_last_error.restype = C.c_char_p
         for name in ("pxm_render_forward", "pxm_render_backward_grid", "pxm_render_backward_pose",
-                     "pxm_tv_grad", "pxm_render_fused", "pxm_render_fused_noalloc",
+                     "pxm_tv_grad", "pxm_tv_grad_set", "pxm_render_fused", "pxm_render_fused_noalloc",
                      "pxm_pose_adam", "pxm_set_tuning",
                      "pxm_grid_upsample_link", "pxm_grid_upsample_data", "pxm_grid_prune"):
             getattr(L, name).restype = C.c_int
@@ -319,12 +320,25 @@ def render_backward_pose(grid, rays, opts, rgb, depth, nsamp, g_rgb, g_depth, gr
 
 
 def tv_grad(grid, lambda_density, lambda_sh, eps, grad_data=None, stream=None):
+    """grad_data += dTV/d record (pxm_tv_grad)."""
     if grad_data is None:
         grad_data = torch.zeros_like(grid.data)
     _need(grad_data, "grad_data", torch.float32, tuple(grid.data.shape))
     g = grid.struct()
     _check("tv_grad", lib().pxm_tv_grad(C.byref(g), float(lambda_density), float(lambda_sh),
                                         float(eps), _ptr(grad_data), _stream(stream)))
+    return grad_data
+
+
+def tv_grad_set(grid, lambda_density, lambda_sh, eps, grad_data=None, stream=None):
+    """grad_data = dTV/d record on the used fields of every linked record
+    (pxm_tv_grad_set); other entries keep their contents."""
+    if grad_data is None:
+        grad_data = torch.zeros_like(grid.data)
+    _need(grad_data, "grad_data", torch.float32, tuple(grid.data.shape))
+    g = grid.struct()
+    _check("tv_grad_set", lib().pxm_tv_grad_set(C.byref(g), float(lambda_density), float(lambda_sh),
+                                                float(eps), _ptr(grad_data), _stream(stream)))
     return grad_data
 
 

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(pxm.EXPORTS) == set(names)
-    assert pxm.abi_version() == 6
+    assert pxm.abi_version() == 7
 
 
 def test_status_strings():
@@ -150,6 +150,10 @@ def test_tv_adam_and_tuning_checks():
     assert L.pxm_tv_grad(C.byref(g), 1.0, 1.0, 0.0, FAKE, None) == 1
     assert L.pxm_tv_grad(C.byref(g), float("nan"), 1.0, 1e-9, FAKE, None) == 1
     assert L.pxm_tv_grad(C.byref(g), 1.0, 1.0, 1e-9, None, None) == 1
+    assert L.pxm_tv_grad_set(C.byref(g), 1.0, 1.0, 0.0, FAKE, None) == 1
+    assert L.pxm_tv_grad_set(C.byref(g), 1.0, float("inf"), 1e-9, FAKE, None) == 1
+    assert L.pxm_tv_grad_set(C.byref(g), 1.0, 1.0, 1e-9, None, None) == 1
+    assert L.pxm_tv_grad_set(C.byref(g), 1.0, 1.0, 1e-9, FAKE + 4, None) == 1   # 16-byte alignment
     assert L.pxm_pose_adam(0, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.999, 1e-8, None) == 1
     assert L.pxm_pose_adam(2, FAKE, FAKE, FAKE, 1e-3, 1.0, 0.999, 1e-8, None) == 1
     assert L.pxm_pose_adam(2, FAKE, FAKE, None, 1e-3, 0.9, 0.999, 1e-8, None) == 1

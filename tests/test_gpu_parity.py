@@ -392,9 +392,11 @@ def test_tv_c2(c2):
     _, ref = oracle.tv(c2.grid, lam_d, lam_sh, eps)
     g = pxm.grid_to_device(c2.grid)
     grad = pxm.tv_grad(g, lam_d, lam_sh, eps)
+    put = pxm.tv_grad_set(g, lam_d, lam_sh, eps, grad_data=torch.ones_like(g.data))
     torch.cuda.synchronize()
     assert_r28(np_(grad)[:, 0], ref[:, 0], TAU_GRAD, "tv density")
     assert_r28(np_(grad)[:, 1:], ref[:, 1:], TAU_GRAD, "tv sh")
+    assert np.array_equal(np_(put), np_(grad))
 
 
 @pytest.mark.parametrize("occupancy", [True, False])
@@ -407,6 +409,23 @@ def test_tv_dense_c1(c1, occupancy):
     grad = pxm.tv_grad(g, 0.3, 0.05, 1e-4, grad_data=base)     # accumulates
     torch.cuda.synchronize()
     assert_r28(np_(grad) - 0.25, ref, TAU_GRAD, "tv dense")
+
+
+@pytest.mark.parametrize("occupancy", [True, False])
+def test_tv_set_writes_the_gradient(c1, occupancy):
+    """pxm_tv_grad_set overwrites the used fields of every linked record with
+    dTV (the oracle's, to the gradient tolerance, whatever the buffer held)
+    and equals pxm_tv_grad on a zeroed buffer value for value."""
+    pxm = _dev()
+    wl, _ = c1
+    _, ref = oracle.tv(wl.grid, 0.3, 0.05, 1e-4)
+    g = pxm.grid_to_device(wl.grid, occupancy=occupancy)
+    junk = torch.full_like(g.data, 7.5)
+    got = np_(pxm.tv_grad_set(g, 0.3, 0.05, 1e-4, grad_data=junk))
+    acc = np_(pxm.tv_grad(g, 0.3, 0.05, 1e-4, grad_data=torch.zeros_like(g.data)))
+    torch.cuda.synchronize()
+    assert_r28(got, ref, TAU_GRAD, "tv set")
+    assert np.array_equal(got, acc)
 
 
 @pytest.mark.parametrize("reso", [(17, 9, 24), (9, 16, 25)])
@@ -429,9 +448,11 @@ def test_tv_ragged_bricks(reso):
     for occ in (True, False):
         g = pxm.grid_to_device(grid, occupancy=occ)
         outs.append(np_(pxm.tv_grad(g, 0.3, 0.05, 1e-4)))
+        outs.append(np_(pxm.tv_grad_set(g, 0.3, 0.05, 1e-4, grad_data=torch.full_like(g.data, -3.0))))
     torch.cuda.synchronize()
     assert_r28(outs[0], ref, TAU_GRAD, f"tv {reso}")
-    assert np.array_equal(outs[0], outs[1])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
 
 
 def test_empty_grid_every_entry_point():
@@ -454,6 +475,7 @@ def test_empty_grid_every_entry_point():
     pxm.render_fused(g, r, wl.opts, t["rgb"], t["depth"], t["fw"], 3, loss=loss, grad_data=gd,
                      grad_pose=gp)
     pxm.tv_grad(g, 0.1, 0.1, 1e-6, gd)
+    pxm.tv_grad_set(g, 0.1, 0.1, 1e-6, gd)
     pxm.grid_rmsprop(g.data, gd, torch.zeros_like(g.data), 0.1, 0.1)
     torch.cuda.synchronize()
     assert np.all(np_(rgb) == 0) and np.all(np_(depth) == 0)

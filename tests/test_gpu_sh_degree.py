@@ -142,10 +142,12 @@ def test_tv(deg):
         g = pxm.grid_to_device(grid)
         base = torch.full_like(g.data, 0.25)
         grad = pxm.tv_grad(g, 0.3, 0.05, 1e-4, grad_data=base)
+        put = pxm.tv_grad_set(g, 0.3, 0.05, 1e-4, grad_data=torch.full_like(g.data, 0.25))
         torch.cuda.synchronize()
         used = oracle.used_fields(deg)
-        assert np.all(np_(grad)[:, used:] == 0.25)
+        assert np.all(np_(grad)[:, used:] == 0.25) and np.all(np_(put)[:, used:] == 0.25)
         assert_r28(np_(grad)[:, :used] - 0.25, ref[:, :used], TAU_GRAD, f"tv {wl.name} deg {deg}")
+        assert_r28(np_(put)[:, :used], ref[:, :used], TAU_GRAD, f"tv set {wl.name} deg {deg}")
 
 
 @pytest.mark.parametrize("deg", DEGREES)
