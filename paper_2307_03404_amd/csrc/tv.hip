@@ -43,6 +43,10 @@ constexpr int TH = TB + 2;
 constexpr int TH3 = TH * TH * TH;       // 216 staged positions
 constexpr int PLANE = TH3 + 1;          // padded field plane: lanes over fields hit distinct banks
 constexpr int TV_THREADS = 256;
+// a listed vertex: its sub-halo position and the TV terms that touch it
+// (its own, and those of its -x, -y, -z neighbours)
+constexpr int TERM_POS = 0xff, TERM_OWN = 0x100, TERM_X = 0x200, TERM_Y = 0x400, TERM_Z = 0x800;
+static_assert(TH3 <= TERM_POS + 1, "sub-halo positions fit in the low byte");
 constexpr int TV_ITEMS = TB * TB * TB * 32 / TV_THREADS;   // vertex-field items per thread, at most
 
 __device__ __forceinline__ int hidx8(int x, int y, int z) { return (x * TH8 + y) * TH8 + z; }
@@ -93,15 +97,27 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
     __syncthreads();
     // sub-brick sb: origin 4 * (bit 2, bit 1, bit 0 of sb) in block-halo
     // coordinates (its halo starts one lower).  Wave w lists sub-bricks w
-    // and w + 4 (64 vertices each, one per lane).
+    // and w + 4 (64 vertices each, one per lane).  An entry holds the
+    // vertex's sub-halo position and which of the four terms touching it
+    // exist (TERM_*), decided once per vertex here rather than per field.
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int sb = t / WAVE + 4 * j, l = t % WAVE;
         const int ox = 4 * ((sb >> 2) & 1), oy = 4 * ((sb >> 1) & 1), oz = 4 * (sb & 1);
         const int ix = l / (TB * TB) + 1, iy = (l / TB) % TB + 1, iz = l % TB + 1;
-        const bool a = s_id8[hidx8(ox + ix, oy + iy, oz + iz)] >= 0;
+        const int h = hidx8(ox + ix, oy + iy, oz + iz);
+        const bool a = s_id8[h] >= 0;
         const unsigned long long m = __ballot(a);
-        if (a) s_list[sb][__popcll(m & ((1ull << l) - 1))] = hidx(ix, iy, iz);
+        if (a) {
+            const int x = x0 + ox + ix - 1, y = y0 + oy + iy - 1, z = z0 + oz + iz - 1;
+            const bool ix_ = x < X - 1, iy_ = y < Y - 1, iz_ = z < Z - 1;
+            int e = hidx(ix, iy, iz);
+            if (ix_ && iy_ && iz_) e |= TERM_OWN;
+            if (x >= 1 && iy_ && iz_ && s_id8[h - TH8 * TH8] >= 0) e |= TERM_X;
+            if (y >= 1 && ix_ && iz_ && s_id8[h - TH8] >= 0) e |= TERM_Y;
+            if (z >= 1 && ix_ && iy_ && s_id8[h - 1] >= 0) e |= TERM_Z;
+            s_list[sb][__popcll(m & ((1ull << l) - 1))] = e;
+        }
         if (l == 0) s_n[sb] = __popcll(m);
     }
     __syncthreads();
@@ -152,34 +168,33 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
         const int* list = s_list[sb];
         // 32 lanes per allocated vertex, lane m < USED takes field m; a thread
         // has at most TV_ITEMS items (n <= 64)
-        auto dtv = [&](int c, int m) -> float {
-            const int ix = c / (TH * TH), iy = (c / TH) % TH, iz = c % TH;
-            const int x = x0 + ox + ix - 1, y = y0 + oy + iy - 1, z = z0 + oz + iz - 1;
+        auto dtv = [&](int e, int m) -> float {
+            const int c = e & TERM_POS;
             const float* plane = s_v[m];
             auto val = [&](int p) -> float { return plane[p]; };
             const float v0 = val(c);
             float acc = 0.f;
-            if (x < X - 1 && y < Y - 1 && z < Z - 1) {
+            if (e & TERM_OWN) {
                 const float dx = val(c + TH * TH) - v0;
                 const float dy = val(c + TH) - v0;
                 const float dz = val(c + 1) - v0;
                 acc -= (dx + dy + dz) * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            if (x >= 1 && y < Y - 1 && z < Z - 1 && s_id[c - TH * TH] >= 0) {
+            if (e & TERM_X) {
                 const float a0 = val(c - TH * TH);
                 const float dx = v0 - a0;
                 const float dy = val(c - TH * TH + TH) - a0;
                 const float dz = val(c - TH * TH + 1) - a0;
                 acc += dx * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            if (y >= 1 && x < X - 1 && z < Z - 1 && s_id[c - TH] >= 0) {
+            if (e & TERM_Y) {
                 const float b0 = val(c - TH);
                 const float dx = val(c - TH + TH * TH) - b0;
                 const float dy = v0 - b0;
                 const float dz = val(c - TH + 1) - b0;
                 acc += dy * rsqrtf(dx * dx + dy * dy + dz * dz + eps);
             }
-            if (z >= 1 && x < X - 1 && y < Y - 1 && s_id[c - 1] >= 0) {
+            if (e & TERM_Z) {
                 const float c0 = val(c - 1);
                 const float dx = val(c - 1 + TH * TH) - c0;
                 const float dy = val(c - 1 + TH) - c0;
@@ -194,8 +209,8 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
                 const int it = t + k * TV_THREADS;
                 const int m = it & 31;
                 if (it < n * 32 && m < USED) {
-                    const int c = list[it >> 5];
-                    grad[(int64_t)s_id[c] * S + m] = dtv(c, m);
+                    const int e = list[it >> 5];
+                    grad[(int64_t)s_id[e & TERM_POS] * S + m] = dtv(e, m);
                 }
             }
         } else {
@@ -210,7 +225,7 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
                 ga[k] = -1;
                 gv[k] = 0.f;
                 if (it < n * 32 && m < USED) {
-                    ga[k] = (int64_t)s_id[list[it >> 5]] * S + m;
+                    ga[k] = (int64_t)s_id[list[it >> 5] & TERM_POS] * S + m;
                     gv[k] = grad[ga[k]];
                 }
             }
