@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pxm {
 
 constexpr int REC = 28;          // floats per record at SH degree 2 (the largest)
@@ -165,10 +167,29 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Sum over the 64 lanes (every lane active), returned to all of them:
+// data-parallel-primitive moves within rows of 16 lanes (shift right by 1,
+// 2, 4, 8), then the last lane of each row broadcast into the next rows,
+// leave the total in lane 63 (a lane with no source lane reads 0).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+    auto step = [&](auto ctrl, auto row_mask) {
+        const uint64_t u = (uint64_t)__double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, decltype(ctrl)::value,
+                                                   decltype(row_mask)::value, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), decltype(ctrl)::value,
+                                                   decltype(row_mask)::value, 0xf, false);
+        v += __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+    };
+    step(std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xf>{});   // row_shr:1
+    step(std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xf>{});   // row_shr:2
+    step(std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xf>{});   // row_shr:4
+    step(std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xf>{});   // row_shr:8
+    step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xa>{});   // row_bcast:15
+    step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xc>{});   // row_bcast:31
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
 __device__ __forceinline__ long long wave_sum(long long v) {
@@ -189,7 +210,7 @@ __device__ __forceinline__ void seg_sum_atomic(int key, bool active, const doubl
     unsigned long long pending = __ballot(active);
     while (pending) {
         int leader = __ffsll((long long)pending) - 1;
-        int k0 = __shfl(key, leader, WAVE);
+        const int k0 = __builtin_amdgcn_readlane(key, leader);
         bool mine = active && (key == k0);
         unsigned long long mask = __ballot(mine);
 #pragma unroll

@@ -201,13 +201,31 @@ __device__ __forceinline__ bool backward_sample(const KGrid& g, const KOpts& op,
     return true;
 }
 
+// Minimum over the 64 lanes (every lane active), returned to all of them.
+// Data-parallel-primitive moves within rows of 16 lanes (shift right by 1,
+// 2, 4, 8), then the last lane of each row broadcast into the next rows,
+// leave the wave's minimum in lane 63; a lane with no source lane reads the
+// identity INT64_MAX.  No LDS round trip, unlike a butterfly of shuffles.
 __device__ __forceinline__ int64_t wave_min(int64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const int64_t o = __shfl_xor(v, m, WAVE);
+    constexpr int ID_LO = -1, ID_HI = 0x7fffffff;            // INT64_MAX
+    auto step = [&](auto ctrl, auto row_mask) {
+        const int lo = __builtin_amdgcn_update_dpp(ID_LO, (int)(uint32_t)v, decltype(ctrl)::value,
+                                                   decltype(row_mask)::value, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(ID_HI, (int)((uint64_t)v >> 32), decltype(ctrl)::value,
+                                                   decltype(row_mask)::value, 0xf, false);
+        const int64_t o = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
         v = o < v ? o : v;
-    }
-    return v;
+    };
+    using std::integral_constant;
+    step(integral_constant<int, 0x111>{}, integral_constant<int, 0xf>{});   // row_shr:1
+    step(integral_constant<int, 0x112>{}, integral_constant<int, 0xf>{});   // row_shr:2
+    step(integral_constant<int, 0x114>{}, integral_constant<int, 0xf>{});   // row_shr:4
+    step(integral_constant<int, 0x118>{}, integral_constant<int, 0xf>{});   // row_shr:8
+    step(integral_constant<int, 0x142>{}, integral_constant<int, 0xa>{});   // row_bcast:15 -> rows 1, 3
+    step(integral_constant<int, 0x143>{}, integral_constant<int, 0xc>{});   // row_bcast:31 -> rows 2, 3
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const int hi = __builtin_amdgcn_readlane((int)((uint64_t)v >> 32), 63);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
 // The smallest marked position offset >= o in a lane's work mask (words
