@@ -13,7 +13,8 @@
 // once, loads the links of the block and its one-vertex halo (10^3) in one
 // pass, and then, for each sub-brick with an allocated vertex, stages the
 // sub-brick's 6^3 halo records with all their fields at once (each record
-// read as one contiguous run: 112 bytes at SH degree 2) and computes its
+// read as one contiguous run: 112 bytes at SH degree 2, and kept in LDS
+// position-major, as it arrived) and computes its
 // vertices' fields (28 at degree 2, 13 at degree 1, 4 at degree 0) with
 // consecutive lanes, so each gradient record is written as one run.
 // (Staging four fields at a time over 8^3 blocks fetched every record line
@@ -41,7 +42,6 @@ constexpr int TH83 = TH8 * TH8 * TH8;   // 1000 link positions
 constexpr int TB = 4;                   // sub-brick edge
 constexpr int TH = TB + 2;
 constexpr int TH3 = TH * TH * TH;       // 216 staged positions
-constexpr int PLANE = TH3 + 1;          // padded field plane: lanes over fields hit distinct banks
 constexpr int TV_THREADS = 256;
 // a listed vertex: its sub-halo position and the TV terms that touch it
 // (its own, and those of its -x, -y, -z neighbours)
@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
     static_assert(TV_THREADS == 4 * WAVE, "one wave lists two sub-bricks");
     __shared__ int s_id8[TH83];             // links of the block halo (-1 empty or outside)
     __shared__ int s_id[TH3];               // links of the current sub-brick halo
-    __shared__ float s_v[S][PLANE];         // field m of sub-halo position p at s_v[m][p]
+    __shared__ float4 s_v4[TH3 * Q];        // the sub-halo records, position-major: field m of
+                                            // position p at float p * S + m
     __shared__ int s_list[8][TB * TB * TB]; // per sub-brick: sub-halo positions of its allocated vertices
     __shared__ int s_n[8];
     const int t = threadIdx.x;
@@ -141,26 +142,22 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
             }
         }
     };
+    // halo offset of sub-halo position t (positions of every sub-brick
+    // differ from it by the sub-brick's origin)
+    const int my_h8 = t < TH3 ? hidx8(t / (TH * TH), (t / TH) % TH, t % TH) : 0;
     int sb = next_nonempty(0);
     if (sb < 8) request(sb);
 #pragma unroll 1
     while (sb < 8) {
         const int ox = 4 * ((sb >> 2) & 1), oy = 4 * ((sb >> 1) & 1), oz = 4 * (sb & 1);
+        // records as they arrived (float4 i of the sub-halo is float4 i of
+        // the position-major block), and the sub-halo links, position t
 #pragma unroll
         for (int k = 0; k < STAGE_ITERS; ++k) {
             const int i = t + k * TV_THREADS;
-            if (i < TH3 * Q) {
-                const int p = i / Q, q = i - Q * p;
-                if (q == 0) {
-                    const int hx = p / (TH * TH), hy = (p / TH) % TH, hz = p % TH;
-                    s_id[p] = s_id8[hidx8(ox + hx, oy + hy, oz + hz)];
-                }
-                s_v[4 * q][p] = wv[k].x;
-                s_v[4 * q + 1][p] = wv[k].y;
-                s_v[4 * q + 2][p] = wv[k].z;
-                s_v[4 * q + 3][p] = wv[k].w;
-            }
+            if (i < TH3 * Q) s_v4[i] = wv[k];
         }
+        if (t < TH3) s_id[t] = s_id8[hidx8(ox, oy, oz) + my_h8];
         __syncthreads();
         const int nx = next_nonempty(sb + 1);
         if (nx < 8) request(nx);                            // in flight while sb is computed
@@ -170,8 +167,8 @@ __global__ void __launch_bounds__(TV_THREADS) k_tv(KGrid g, float lam_d, float l
         // has at most TV_ITEMS items (n <= 64)
         auto dtv = [&](int e, int m) -> float {
             const int c = e & TERM_POS;
-            const float* plane = s_v[m];
-            auto val = [&](int p) -> float { return plane[p]; };
+            const float* field = reinterpret_cast<const float*>(s_v4) + m;
+            auto val = [&](int p) -> float { return field[p * S]; };
             const float v0 = val(c);
             float acc = 0.f;
             if (e & TERM_OWN) {
